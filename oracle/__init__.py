@@ -1,0 +1,39 @@
+"""Oracle: a plain, slow, CPU implementation of the online approximate k-nn
+graph builder of "Fast Online k-nn Graph Building" (Debatty, Michiardi &
+Mees, arXiv 1602.06819).
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  Only the tests, the smoke check of the
+build entry point and the CPU-baseline leg of the benchmark may import it.
+The product path (the HIP library and its Python binding) never imports,
+calls or links anything here, and this package imports nothing from the
+product.  The only code both sides share is the seeded input generator
+package ``datagen``, which holds none of the method's arithmetic.
+
+What is computed, step by step (the readings of points where the paper is
+silent are listed in each function's docstring):
+
+* exact k-nn graph by brute force (Section 2.1, "naive method"; Section
+  8.5.2 uses it as ground truth)            -> :func:`exact.exact_graph`
+* improved graph nearest-neighbour search, iGNNS (Section 3: random restart
+  with the expansion test, eager first-improvement step, budget stop after
+  n / speedup similarities)                   -> :func:`ignns.ignns`
+* online insertion: search then Update (Algorithms 1 and 2), with explicit
+  batch semantics; batch size 1 is the paper's sequential insertion
+                                              -> :func:`online.insert_batch`
+* the literal sequential transcription of Algorithms 1 and 2 (adds happen
+  immediately), used to pin the batch form    -> :func:`online.insert_sequential_literal`
+* read-only k-nn query on the current graph   -> :func:`online.query`
+
+Parity status: every function is pinned by tests under ``tests/`` against
+brute force, special cases, closed forms or invariants; the approximation
+quality of the search (which neighbours a given budget finds) has no printed
+value in the paper and is "parity unpinned" beyond those properties.
+"""
+
+from .distance import sqdist, sqdist_many, INF_INT  # noqa: F401
+from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
+from .exact import exact_graph, exact_graph_loops, exact_row  # noqa: F401
+from .graph import OracleGraph, Params, budget  # noqa: F401
+from .ignns import ignns, SearchResult  # noqa: F401
+from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401
+                     BatchResult, QUERY_KEY_BASE)

@@ -1,0 +1,206 @@
+/*
+ * knng.h -- C ABI of the MI355X (gfx950) online approximate k-nn graph
+ * builder of "Fast Online k-nn Graph Building" (Debatty, Michiardi & Mees,
+ * arXiv 1602.06819).
+ *
+ * One GPU holds one graph: the points, one adjacency list of the k most
+ * similar nodes per node (Section 1), and the bookkeeping for insertion.
+ * Dissimilarity is the squared Euclidean distance (the paper's synthetic
+ * data uses Euclidean distance, Section 8.1.1; squaring keeps the order).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory.  The library never allocates device memory.  The caller owns
+ *    and allocates the graph storage and the workspace (sizes from
+ *    knng_storage_bytes / knng_workspace_bytes, 256-byte aligned device
+ *    pointers) and every input/output buffer.  Pointers named *_dev are
+ *    device pointers; *_host are host pointers.  The handle keeps the
+ *    storage and workspace pointers (they must outlive it) but no input or
+ *    output pointer.
+ *  - Streams.  Every call only enqueues work on `stream` (stream-ordered);
+ *    inputs must stay valid, and outputs are only complete, once the stream
+ *    has passed the call.  Calls on one handle must be issued on one stream
+ *    (or ordered by the caller); calls on one handle are not thread safe.
+ *  - Lists.  A list row holds min(k, n-1) entries sorted by the key
+ *    (distance, id) ascending -- ties in distance go to the smaller id --
+ *    followed by padding entries (id -1, distance INT32_MAX for uint8 data,
+ *    +inf for float data).
+ *  - Errors.  Every check (arguments, capacity, state) happens before any
+ *    launch; on error nothing is enqueued and the graph is unchanged, so an
+ *    insert is all-or-nothing.  knng_last_error() gives a thread-local text.
+ *    A failed launch or an asynchronous device fault reported by HIP is
+ *    returned as KNNG_EDEVICE.  No C++ exception crosses this ABI.
+ */
+#ifndef KNNG_H
+#define KNNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct knng_graph knng_graph;   /* opaque handle */
+
+typedef enum {
+  KNNG_OK = 0,
+  KNNG_EINVAL = -1,     /* invalid argument or unsupported combination   */
+  KNNG_ECAPACITY = -2,  /* n + b would exceed params.capacity, or a call
+                           exceeds params.max_batch                         */
+  KNNG_ENOMEM = -3,     /* storage or workspace smaller than required      */
+  KNNG_EDEVICE = -4,    /* a HIP call failed                               */
+  KNNG_ESTATE = -5      /* call not valid in the handle's state            */
+} knng_status;
+
+typedef enum { KNNG_U8 = 0, KNNG_F32 = 1 } knng_dtype;
+typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } knng_score;
+
+/*
+ * Parameters (Section 3 and Algorithm 2 of the paper).
+ *  dim        coordinates per point, 1 .. 4096.
+ *  k          list length, 1 .. 64.
+ *  dtype      KNNG_U8: uint8 points, exact integer distances (int32);
+ *             KNNG_F32: float32 points, float distances.
+ *  score      KNNG_U8 requires KNNG_SCORE_EXACT.
+ *  capacity   largest number of nodes the graph may ever hold (< 2^31).
+ *  max_batch  largest batch (insert) or query count per call.
+ *  speedup    iGNNS budget: B(n) = min(n, max(k, ceil(n / speedup)))
+ *             similarity computations per search (Section 3), >= 1.
+ *  expansion_num / expansion_den
+ *             expansion coefficient e = num / den > 1 (Section 3): a random
+ *             restart node r is discarded iff
+ *             den * (1 + d_r) > num * (1 + d_best), i.e. similarity
+ *             1 / (1 + d) below s_max / e.
+ *  depth      DEPTH of the Update procedure (Algorithm 2): 1 or 2.
+ *  seed       seed of the restart permutations (see knng_search).
+ */
+typedef struct {
+  int32_t  dim;
+  int32_t  k;
+  int32_t  dtype;          /* knng_dtype */
+  int32_t  score;          /* knng_score */
+  int64_t  capacity;
+  int64_t  max_batch;
+  int32_t  speedup;
+  int32_t  expansion_num;
+  int32_t  expansion_den;
+  int32_t  depth;
+  uint64_t seed;
+} knng_params;
+
+/* Bytes of graph storage for params->capacity nodes (0 if params are
+ * invalid; see knng_last_error). */
+size_t knng_storage_bytes(const knng_params* params);
+
+/* Bytes of workspace needed for calls of up to params->max_batch points
+ * (0 if params are invalid). */
+size_t knng_workspace_bytes(const knng_params* params);
+
+/*
+ * Build the exact k-nn graph of n points by brute force and return a new
+ * handle in *out (Section 2.1, naive method: every pairwise distance, keep
+ * the k best per node; Section 8.5.2 builds its initial and ground-truth
+ * graphs this way).
+ *  x_dev   [n][dim] uint8 or float32, row-major, device memory.
+ *  n       2 .. capacity (lists hold min(k, n-1) entries).
+ * The points are copied into the storage; node ids are 0 .. n-1.
+ */
+knng_status knng_build_exact(const knng_params* params, const void* x_dev, int64_t n,
+                             void* storage_dev, size_t storage_bytes,
+                             void* workspace_dev, size_t workspace_bytes,
+                             hipStream_t stream, knng_graph** out);
+
+/*
+ * Create a handle from points and lists supplied by the caller (for
+ * example a saved graph).  ids_dev [n][k] int32 and d_dev [n][k] (int32 for
+ * uint8 data, float for float data) must already satisfy the list
+ * convention above; they are copied into the storage.
+ */
+knng_status knng_load(const knng_params* params, const void* x_dev, int64_t n,
+                      const int32_t* ids_dev, const void* d_dev,
+                      void* storage_dev, size_t storage_bytes,
+                      void* workspace_dev, size_t workspace_bytes,
+                      hipStream_t stream, knng_graph** out);
+
+/*
+ * iGNNS search (Section 3) of m points against the current graph, with
+ * explicit restart keys.  Per query: random restarts drawn without
+ * replacement along a keyed permutation of [0, n) (full-period LCG modulo
+ * 2^ceil(log2 n), parameters from SplitMix64 of (seed, key)), each
+ * discarded by the expansion test; eager first-improvement climbing along
+ * the stored lists; stop right after B(n) distance evaluations.  Evaluated
+ * nodes are never evaluated again.  The result is the k best evaluated
+ * nodes by (distance, id).
+ *  q_dev      [m][dim] points (uint8 or float32), device.
+ *  keys_dev   [m] uint64 restart keys, device (an insert uses its new id).
+ *  ids_dev    [m][k] int32 out;  d_dev [m][k] int32 / float out.
+ *  evals_dev  [m] int32 out (distance evaluations), or NULL.
+ *  trace_dev  [m][trace_stride] int32 out: evaluated ids in evaluation
+ *             order, -1 after the last; or NULL.  trace_stride >= B(n).
+ * Read-only with respect to the graph.  m <= max_batch.
+ */
+knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
+                        const uint64_t* keys_dev, int32_t* ids_dev, void* d_dev,
+                        int32_t* evals_dev, int32_t* trace_dev, int64_t trace_stride,
+                        hipStream_t stream);
+
+/*
+ * Insert a batch of b points (Algorithms 1 and 2, batch form).  With n the
+ * size before the call, the points get ids n .. n+b-1 and:
+ *  (i)   each is searched with iGNNS on the pre-batch graph, key = its id;
+ *  (ii)  its list is the k best of its search result and the other batch
+ *        points;
+ *  (iii) Update: from its search result, nodes up to DEPTH-1 hops away along
+ *        the pre-batch lists are each visited once; each receives a proposal
+ *        (node, distance, new id);
+ *  (iv)  every pre-batch list becomes the k best of itself and its
+ *        proposals by (distance, id).
+ * b = 1 is the paper's sequential insertion.
+ *  x_dev          [b][dim] points, device.
+ *  first_id_host  out: n (ids are first_id .. first_id + b - 1), or NULL.
+ *  sims_dev       [b] int32 out: similarities spent per point (search
+ *                 evaluations + (b - 1) peers + update evaluations), or NULL.
+ * Needs n + b <= capacity (KNNG_ECAPACITY otherwise) and b <= max_batch.
+ */
+knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
+                              int64_t* first_id_host, int32_t* sims_dev,
+                              hipStream_t stream);
+
+/*
+ * Read-only k-nn query of m points on the current graph: iGNNS with the
+ * keys 2^62 + s, where s counts every query this handle has answered
+ * before (the first query of a handle has s = 0).
+ *  ids_dev [m][k] int32, d_dev [m][k] int32/float, evals_dev [m] or NULL.
+ */
+knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m,
+                       int32_t* ids_dev, void* d_dev, int32_t* evals_dev,
+                       hipStream_t stream);
+
+/* Copy lists of nodes [first, first + count) out: ids_dev [count][k] int32,
+ * d_dev [count][k] int32/float (either may be NULL). */
+knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,
+                           int32_t* ids_dev, void* d_dev, hipStream_t stream);
+
+/* Copy points [first, first + count) out as [count][dim] in the input dtype. */
+knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count,
+                            void* x_dev, hipStream_t stream);
+
+/* Number of nodes (counting every insert already enqueued). */
+int64_t knng_size(const knng_graph* g);
+
+/* Number of queries answered by knng_query so far (the next query's s). */
+int64_t knng_query_count(const knng_graph* g);
+
+/* Thread-local text of the last error ("" if none). */
+const char* knng_last_error(void);
+
+/* Free the handle (no device memory is freed: the caller owns it). */
+void knng_destroy(knng_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNG_H */

@@ -32,7 +32,7 @@ value in the paper and is "parity unpinned" beyond those properties.
 
 from .distance import sqdist, sqdist_many, INF_INT  # noqa: F401
 from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
-from .exact import exact_graph, exact_graph_loops, exact_row  # noqa: F401
+from .exact import ExactRows, exact_graph, exact_graph_loops, exact_row  # noqa: F401
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
 from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401

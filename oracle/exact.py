@@ -143,3 +143,39 @@ def _float_row(X, u, kk, vals, idx, m, n, norm_u, max_norm):
     if vals[m - 1] - err > kth:
         return [(float(cd[j]), int(cv[j])) for j in o]
     return exact_row(X, u, kk)
+
+
+class ExactRows:
+    """Exact lists of single points against a fixed point set, one at a
+    time, by the same definition as :func:`exact_graph` (used to check
+    sampled rows of large graphs).  Distances come from the float64 Gram
+    form; for uint8 points they are exact integers; float rows are
+    recomputed in the direct form."""
+
+    def __init__(self, X: np.ndarray, k: int):
+        self.X = X
+        self.k = k
+        self.Xf = X.astype(np.float64)
+        self.norms = np.einsum("ij,ij->i", self.Xf, self.Xf)
+        self.is_int = X.dtype == np.uint8
+
+    def row(self, q: np.ndarray, exclude: int | None = None):
+        n = self.X.shape[0]
+        qf = q.astype(np.float64)
+        D = self.norms + float(qf @ qf) - 2.0 * (self.Xf @ qf)
+        if exclude is not None:
+            D[exclude] = np.inf
+        kk = min(self.k, n - (1 if exclude is not None else 0))
+        m = min(n - 1, kk + _EXTRA)
+        if not self.is_int or m < kk + 1:
+            return exact_row(self.X, 0, kk, q=q, exclude=exclude)
+        D = np.rint(D)
+        cand = np.argpartition(D, m)[: m + 1]      # the m + 1 smallest
+        cd = D[cand]
+        order = np.lexsort((cand, cd))
+        cand, cd = cand[order], cd[order]
+        # every point outside the candidate set is at least cd[-1] away; the
+        # set is complete for the first kk iff nothing outside can tie them
+        if not cd[-1] > cd[kk - 1]:
+            return exact_row(self.X, 0, kk, q=q, exclude=exclude)
+        return [(int(cd[j]), int(cand[j])) for j in range(kk)]

@@ -1,0 +1,546 @@
+// C ABI of the library (declared in include/knng.h): argument validation,
+// storage/workspace layout and stream-ordered kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "internal.h"
+#include "knng.h"
+
+using namespace knng;
+
+struct knng_graph {
+  knng_params p;
+  StorageLayout S;
+  WorkspaceLayout W;
+  char* st;
+  size_t st_bytes;
+  char* ws;
+  size_t ws_bytes;
+  int64_t n;
+  int64_t qcount;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+knng_status fail(knng_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+knng_status ok() {
+  g_err.clear();
+  return KNNG_OK;
+}
+
+knng_status dev(hipError_t e, const char* what) {
+  if (e == hipSuccess) return KNNG_OK;
+  return fail(KNNG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define KNNG_TRY(expr, what)                      \
+  do {                                            \
+    knng_status _s = dev((expr), (what));         \
+    if (_s != KNNG_OK) return _s;                 \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int64_t PARTIAL_LISTS = 32768;
+constexpr int64_t QUERY_KEY_BASE = (int64_t)1 << 62;
+
+size_t take(size_t& cur, size_t bytes) {
+  size_t off = cur;
+  cur = (size_t)round_up((int64_t)(cur + bytes), ALIGN);
+  return off;
+}
+
+int k_pad_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+knng_status check_params(const knng_params* p) {
+  if (!p) return fail(KNNG_EINVAL, "params is NULL");
+  if (p->dim < 1 || p->dim > 4096) return fail(KNNG_EINVAL, "dim %d outside 1..4096", p->dim);
+  if (p->k < 1 || p->k > 64) return fail(KNNG_EINVAL, "k %d outside 1..64", p->k);
+  if (p->dtype != KNNG_U8 && p->dtype != KNNG_F32)
+    return fail(KNNG_EINVAL, "unknown dtype %d", p->dtype);
+  if (p->dtype == KNNG_F32)
+    return fail(KNNG_EINVAL, "dtype KNNG_F32 is not available in this build");
+  if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
+    return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
+  if (p->dtype == KNNG_U8 && p->dim > 256)
+    return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
+  if (p->capacity < 2 || p->capacity >= ((int64_t)1 << 31))
+    return fail(KNNG_EINVAL, "capacity %lld outside 2 .. 2^31-1", (long long)p->capacity);
+  if (p->max_batch < 1 || p->max_batch > p->capacity)
+    return fail(KNNG_EINVAL, "max_batch %lld outside 1 .. capacity", (long long)p->max_batch);
+  if (p->speedup < 1) return fail(KNNG_EINVAL, "speedup must be >= 1");
+  if (p->expansion_den < 1 || p->expansion_num <= p->expansion_den)
+    return fail(KNNG_EINVAL, "expansion num/den must be > 1 with den >= 1");
+  if (p->depth < 1 || p->depth > 2) return fail(KNNG_EINVAL, "depth must be 1 or 2");
+  return KNNG_OK;
+}
+
+StorageLayout storage_layout(const knng_params& p) {
+  StorageLayout S;
+  S.dim = p.dim;
+  S.k = p.k;
+  S.k_pad = k_pad_of(p.k);
+  S.row_bytes = (int)round_up(p.dim, 16);
+  S.cap = p.capacity;
+  size_t cur = 0;
+  S.off_vec = take(cur, (size_t)S.cap * S.row_bytes);
+  S.off_norms = take(cur, (size_t)S.cap * 4);
+  S.off_ids = take(cur, (size_t)S.cap * S.k_pad * 4);
+  S.off_dist = take(cur, (size_t)S.cap * S.k_pad * 4);
+  S.off_head = take(cur, (size_t)S.cap * 4);
+  S.total = cur;
+  return S;
+}
+
+WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
+  WorkspaceLayout W;
+  W.M = p.max_batch;
+  W.props_per_point = (int64_t)p.k + (int64_t)p.k * p.k;
+  W.partial_lists = PARTIAL_LISTS;
+  size_t cur = 0;
+  const size_t M = (size_t)W.M;
+  W.off_qvec = take(cur, M * S.row_bytes);
+  W.off_qnorm = take(cur, M * 4);
+  W.off_res_ids = take(cur, M * S.k_pad * 4);
+  W.off_res_d = take(cur, M * S.k_pad * 4);
+  W.off_evals = take(cur, M * 4);
+  W.off_upd = take(cur, M * 4);
+  W.off_props = take(cur, M * (size_t)W.props_per_point * sizeof(Proposal));
+  W.off_touched = take(cur, M * (size_t)W.props_per_point * 4);
+  W.off_counters = take(cur, 256);
+  W.off_partial = take(cur, (size_t)W.partial_lists * S.k_pad * 8);
+  W.off_keys = take(cur, M * 8);
+  W.total = cur;
+  return W;
+}
+
+template <class T>
+T* at(char* base, size_t off) {
+  return reinterpret_cast<T*>(base + off);
+}
+
+int64_t budget(int64_t n, int k, int speedup) {
+  int64_t b = (n + speedup - 1) / speedup;
+  if (b < k) b = k;
+  if (b > n) b = n;
+  return b;
+}
+
+uint32_t modulus_for(int64_t n) {
+  uint32_t m = 1;
+  while ((int64_t)m < n) m <<= 1;
+  return m;
+}
+
+knng_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(KNNG_EINVAL, "%s is NULL", name);
+  return KNNG_OK;
+}
+
+knng_status make_handle(const knng_params* p, void* storage, size_t storage_bytes,
+                        void* workspace, size_t workspace_bytes, knng_graph** out) {
+  knng_status s = check_params(p);
+  if (s != KNNG_OK) return s;
+  if (!out) return fail(KNNG_EINVAL, "out is NULL");
+  if (!storage || !workspace) return fail(KNNG_EINVAL, "storage or workspace is NULL");
+  if (((uintptr_t)storage % ALIGN) || ((uintptr_t)workspace % ALIGN))
+    return fail(KNNG_EINVAL, "storage and workspace must be 256-byte aligned");
+  StorageLayout S = storage_layout(*p);
+  WorkspaceLayout W = workspace_layout(*p, S);
+  if (storage_bytes < S.total)
+    return fail(KNNG_ENOMEM, "storage has %zu bytes, needs %zu", storage_bytes, S.total);
+  if (workspace_bytes < W.total)
+    return fail(KNNG_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, W.total);
+  knng_graph* g = new (std::nothrow) knng_graph;
+  if (!g) return fail(KNNG_ENOMEM, "host allocation failed");
+  g->p = *p;
+  g->S = S;
+  g->W = W;
+  g->st = (char*)storage;
+  g->st_bytes = storage_bytes;
+  g->ws = (char*)workspace;
+  g->ws_bytes = workspace_bytes;
+  g->n = 0;
+  g->qcount = 0;
+  *out = g;
+  return KNNG_OK;
+}
+
+// Search m ingested query rows (at qvec/qnorm) on the current graph.
+knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, int64_t m,
+                       const uint64_t* keys, uint64_t key_base, int32_t* out_ids,
+                       int32_t* out_d, int out_stride, int32_t* evals, int32_t* trace,
+                       int64_t trace_stride, hipStream_t stream) {
+  const StorageLayout& S = g->S;
+  SearchArgs a{};
+  a.vec = at<int8_t>(g->st, S.off_vec);
+  a.row_bytes = S.row_bytes;
+  a.nbr_ids = at<int32_t>(g->st, S.off_ids);
+  a.k = S.k;
+  a.k_pad = S.k_pad;
+  a.n = (int32_t)g->n;
+  a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
+  a.m_mod = modulus_for(g->n);
+  a.e_num = g->p.expansion_num;
+  a.e_den = g->p.expansion_den;
+  a.seed = g->p.seed;
+  a.qvec = qvec;
+  a.qnorm = qnorm;
+  a.m = (int32_t)m;
+  a.keys = keys;
+  a.key_base = key_base;
+  a.out_ids = out_ids;
+  a.out_d = out_d;
+  a.out_stride = out_stride;
+  a.out_evals = evals;
+  a.trace = trace;
+  a.trace_stride = trace_stride;
+  a.vis_words = (int32_t)((g->n + 31) / 32);
+  if ((size_t)a.vis_words * 4 > 65536)
+    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
+                             "which this build does not provide");
+  KNNG_TRY(launch_search_u8(a, stream), "search launch");
+  return KNNG_OK;
+}
+
+knng_status ingest(knng_graph* g, const void* x, int64_t m, int8_t* dst, int32_t* norms,
+                   hipStream_t stream) {
+  IngestArgs a{};
+  a.x = (const uint8_t*)x;
+  a.dst = dst;
+  a.norms = norms;
+  a.m = m;
+  a.dim = g->S.dim;
+  a.row_bytes = g->S.row_bytes;
+  KNNG_TRY(launch_ingest_u8(a, stream), "ingest launch");
+  return KNNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t knng_storage_bytes(const knng_params* p) {
+  if (check_params(p) != KNNG_OK) return 0;
+  return storage_layout(*p).total;
+}
+
+size_t knng_workspace_bytes(const knng_params* p) {
+  if (check_params(p) != KNNG_OK) return 0;
+  return workspace_layout(*p, storage_layout(*p)).total;
+}
+
+knng_status knng_build_exact(const knng_params* p, const void* x_dev, int64_t n,
+                             void* storage_dev, size_t storage_bytes, void* workspace_dev,
+                             size_t workspace_bytes, hipStream_t stream, knng_graph** out) {
+  if (out) *out = nullptr;
+  knng_status s = check_params(p);
+  if (s != KNNG_OK) return s;
+  if ((s = check_ptr(x_dev, "x_dev")) != KNNG_OK) return s;
+  if (n < 2) return fail(KNNG_EINVAL, "n must be >= 2 (got %lld)", (long long)n);
+  if (n > p->capacity)
+    return fail(KNNG_ECAPACITY, "n %lld exceeds capacity %lld", (long long)n,
+                (long long)p->capacity);
+  knng_graph* g = nullptr;
+  s = make_handle(p, storage_dev, storage_bytes, workspace_dev, workspace_bytes, &g);
+  if (s != KNNG_OK) return s;
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  int8_t* vec = at<int8_t>(g->st, S.off_vec);
+  int32_t* norms = at<int32_t>(g->st, S.off_norms);
+  int32_t* ids = at<int32_t>(g->st, S.off_ids);
+  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  auto cleanup = [&](knng_status st) {
+    delete g;
+    return st;
+  };
+  if ((s = ingest(g, x_dev, n, vec, norms, stream)) != KNNG_OK) return cleanup(s);
+  if ((s = dev(launch_fill_i32(at<int32_t>(g->st, S.off_head), S.cap, -1, stream), "fill")) !=
+      KNNG_OK)
+    return cleanup(s);
+
+  ExactArgs a{};
+  a.qvec = vec;
+  a.qnorm = norms;
+  a.nq = (int32_t)n;
+  a.q_id_base = 0;
+  a.dvec = vec;
+  a.dnorm = norms;
+  a.nd = (int32_t)n;
+  a.d_id_base = 0;
+  a.row_bytes = S.row_bytes;
+  a.k = S.k;
+  a.exclude_self = 1;
+  a.out_ids = ids;
+  a.out_d = dist;
+  a.out_stride = S.k_pad;
+  a.partial = at<uint64_t>(g->ws, W.off_partial);
+  const int qt = S.k_pad == 64 ? 1 : 2;
+  const int64_t bx = (n + 64 * qt - 1) / (64 * qt);
+  int64_t nsplit = (1024 + bx - 1) / bx;
+  if (nsplit > 64) nsplit = 64;
+  while (nsplit > 1 && nsplit * n > W.partial_lists) --nsplit;
+  if (nsplit < 1) nsplit = 1;
+  int64_t split_len = round_up((n + nsplit - 1) / nsplit, 64);
+  nsplit = (n + split_len - 1) / split_len;
+  a.split_len = (int32_t)split_len;
+  a.nsplit = (int32_t)nsplit;
+  if ((s = dev(launch_exact_u8(a, stream), "exact launch")) != KNNG_OK) return cleanup(s);
+  if (nsplit > 1) {
+    if ((s = dev(launch_split_merge(a.partial, (int32_t)n, (int32_t)nsplit, S.k, ids, dist,
+                                    S.k_pad, stream),
+                 "split merge launch")) != KNNG_OK)
+      return cleanup(s);
+  }
+  g->n = n;
+  *out = g;
+  return ok();
+}
+
+knng_status knng_load(const knng_params* p, const void* x_dev, int64_t n, const int32_t* ids_dev,
+                      const void* d_dev, void* storage_dev, size_t storage_bytes,
+                      void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                      knng_graph** out) {
+  if (out) *out = nullptr;
+  knng_status s = check_params(p);
+  if (s != KNNG_OK) return s;
+  if ((s = check_ptr(x_dev, "x_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  if (n < 2) return fail(KNNG_EINVAL, "n must be >= 2 (got %lld)", (long long)n);
+  if (n > p->capacity)
+    return fail(KNNG_ECAPACITY, "n %lld exceeds capacity %lld", (long long)n,
+                (long long)p->capacity);
+  knng_graph* g = nullptr;
+  s = make_handle(p, storage_dev, storage_bytes, workspace_dev, workspace_bytes, &g);
+  if (s != KNNG_OK) return s;
+  const StorageLayout& S = g->S;
+  auto cleanup = [&](knng_status st) {
+    delete g;
+    return st;
+  };
+  if ((s = ingest(g, x_dev, n, at<int8_t>(g->st, S.off_vec), at<int32_t>(g->st, S.off_norms),
+                  stream)) != KNNG_OK)
+    return cleanup(s);
+  if ((s = dev(launch_fill_i32(at<int32_t>(g->st, S.off_head), S.cap, -1, stream), "fill")) !=
+      KNNG_OK)
+    return cleanup(s);
+  if ((s = dev(launch_copy_lists(ids_dev, (const int32_t*)d_dev, S.k,
+                                 at<int32_t>(g->st, S.off_ids), at<int32_t>(g->st, S.off_dist),
+                                 S.k_pad, n, S.k, n, stream),
+               "copy lists")) != KNNG_OK)
+    return cleanup(s);
+  g->n = n;
+  *out = g;
+  return ok();
+}
+
+knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint64_t* keys_dev,
+                        int32_t* ids_dev, void* d_dev, int32_t* evals_dev, int32_t* trace_dev,
+                        int64_t trace_stride, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (m == 0) return ok();
+  if (m < 0) return fail(KNNG_EINVAL, "m must be >= 0");
+  if (m > g->W.M)
+    return fail(KNNG_ECAPACITY, "m %lld exceeds max_batch %lld", (long long)m,
+                (long long)g->W.M);
+  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  if (trace_dev && trace_stride < budget(g->n, g->S.k, g->p.speedup))
+    return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
+                (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
+  if ((g->n + 31) / 32 * 4 > 65536)
+    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
+                             "which this build does not provide");
+  const WorkspaceLayout& W = g->W;
+  int8_t* qv = at<int8_t>(g->ws, W.off_qvec);
+  int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
+  if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
+  s = run_search(g, qv, qn, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
+                 trace_dev, trace_stride, stream);
+  if (s != KNNG_OK) return s;
+  return ok();
+}
+
+knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids_dev,
+                       void* d_dev, int32_t* evals_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (m == 0) return ok();
+  if (m < 0) return fail(KNNG_EINVAL, "m must be >= 0");
+  if (m > g->W.M)
+    return fail(KNNG_ECAPACITY, "m %lld exceeds max_batch %lld", (long long)m,
+                (long long)g->W.M);
+  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  if ((g->n + 31) / 32 * 4 > 65536)
+    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
+                             "which this build does not provide");
+  const WorkspaceLayout& W = g->W;
+  int8_t* qv = at<int8_t>(g->ws, W.off_qvec);
+  int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
+  if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
+  s = run_search(g, qv, qn, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
+                 (int32_t*)d_dev, g->S.k, evals_dev, nullptr, 0, stream);
+  if (s != KNNG_OK) return s;
+  g->qcount += m;
+  return ok();
+}
+
+knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
+                              int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (b == 0) {
+    if (first_id_host) *first_id_host = g->n;
+    return ok();
+  }
+  if (b < 0) return fail(KNNG_EINVAL, "b must be >= 0");
+  if ((s = check_ptr(x_dev, "x_dev")) != KNNG_OK) return s;
+  if (b > g->W.M)
+    return fail(KNNG_ECAPACITY, "batch %lld exceeds max_batch %lld", (long long)b,
+                (long long)g->W.M);
+  if (g->n + b > g->S.cap)
+    return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
+                (long long)b, (long long)g->S.cap);
+  if ((g->n + b + 31) / 32 * 4 > 65536)
+    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
+                             "which this build does not provide");
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  const int64_t n = g->n;
+  int8_t* vec = at<int8_t>(g->st, S.off_vec);
+  int32_t* norms = at<int32_t>(g->st, S.off_norms);
+  int32_t* ids = at<int32_t>(g->st, S.off_ids);
+  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  int32_t* head = at<int32_t>(g->st, S.off_head);
+  int32_t* res_ids = at<int32_t>(g->ws, W.off_res_ids);
+  int32_t* res_d = at<int32_t>(g->ws, W.off_res_d);
+  int32_t* evals = at<int32_t>(g->ws, W.off_evals);
+  int32_t* counters = at<int32_t>(g->ws, W.off_counters);
+  int8_t* bvec = vec + n * S.row_bytes;
+  int32_t* bnorm = norms + n;
+
+  // (0) the new points, stored at their ids (not visible to the search,
+  //     which only reads nodes < n)
+  if ((s = ingest(g, x_dev, b, bvec, bnorm, stream)) != KNNG_OK) return s;
+  // (i) iGNNS of every new point on the pre-batch graph, key = its id
+  s = run_search(g, bvec, bnorm, b, nullptr, (uint64_t)n, res_ids, res_d, S.k_pad, evals,
+                 nullptr, 0, stream);
+  if (s != KNNG_OK) return s;
+  // (ii) lists of the new nodes: search result + batch peers
+  PeerArgs pa{};
+  pa.bvec = bvec;
+  pa.bnorm = bnorm;
+  pa.b = (int32_t)b;
+  pa.id_base = (int32_t)n;
+  pa.row_bytes = S.row_bytes;
+  pa.k = S.k;
+  pa.k_pad = S.k_pad;
+  pa.res_ids = res_ids;
+  pa.res_d = res_d;
+  pa.list_ids = ids + n * S.k_pad;
+  pa.list_d = dist + n * S.k_pad;
+  KNNG_TRY(launch_peers_u8(pa, stream), "peers launch");
+  // (iii) update proposals on the pre-batch lists
+  KNNG_TRY(launch_fill_i32(counters, 2, 0, stream), "fill");
+  UpdateArgs ua{};
+  ua.vec = vec;
+  ua.row_bytes = S.row_bytes;
+  ua.nbr_ids = ids;
+  ua.nbr_d = dist;
+  ua.k = S.k;
+  ua.k_pad = S.k_pad;
+  ua.head = head;
+  ua.bvec = bvec;
+  ua.bnorm = bnorm;
+  ua.b = (int32_t)b;
+  ua.id_base = (int32_t)n;
+  ua.res_ids = res_ids;
+  ua.res_d = res_d;
+  ua.depth = g->p.depth;
+  ua.props = at<Proposal>(g->ws, W.off_props);
+  ua.touched = at<int32_t>(g->ws, W.off_touched);
+  ua.counters = counters;
+  ua.evals = evals;
+  ua.sims = sims_dev;
+  int hc = 64;
+  while (hc < 2 * W.props_per_point) hc <<= 1;
+  ua.hash_cap = hc;
+  KNNG_TRY(launch_update_u8(ua, stream), "update launch");
+  // (iv) merge proposals into the pre-batch lists
+  MergeArgs ma{};
+  ma.nbr_ids = ids;
+  ma.nbr_d = dist;
+  ma.k = S.k;
+  ma.k_pad = S.k_pad;
+  ma.head = head;
+  ma.props = ua.props;
+  ma.touched = ua.touched;
+  ma.counters = counters;
+  ma.max_touched = (int32_t)(b * W.props_per_point);
+  KNNG_TRY(launch_merge(ma, stream), "merge launch");
+  // (v)
+  if (first_id_host) *first_id_host = n;
+  g->n = n + b;
+  return ok();
+}
+
+knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count, int32_t* ids_dev,
+                           void* d_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (first < 0 || count < 0 || first + count > g->n)
+    return fail(KNNG_EINVAL, "rows [%lld, %lld) outside the graph of %lld nodes",
+                (long long)first, (long long)(first + count), (long long)g->n);
+  if (count == 0) return ok();
+  const StorageLayout& S = g->S;
+  KNNG_TRY(launch_copy_lists(at<int32_t>(g->st, S.off_ids) + first * S.k_pad,
+                             at<int32_t>(g->st, S.off_dist) + first * S.k_pad, S.k_pad, ids_dev,
+                             (int32_t*)d_dev, S.k, count, S.k, g->n, stream),
+           "copy lists");
+  return ok();
+}
+
+knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count, void* x_dev,
+                            hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (!x_dev) return fail(KNNG_EINVAL, "x_dev is NULL");
+  if (first < 0 || count < 0 || first + count > g->n)
+    return fail(KNNG_EINVAL, "rows outside the graph");
+  if (count == 0) return ok();
+  const StorageLayout& S = g->S;
+  KNNG_TRY(launch_export_u8(at<int8_t>(g->st, S.off_vec) + first * S.row_bytes, S.row_bytes,
+                            S.dim, count, (uint8_t*)x_dev, stream),
+           "export points");
+  return ok();
+}
+
+int64_t knng_size(const knng_graph* g) { return g ? g->n : -1; }
+
+int64_t knng_query_count(const knng_graph* g) { return g ? g->qcount : -1; }
+
+const char* knng_last_error(void) { return g_err.c_str(); }
+
+void knng_destroy(knng_graph* g) { delete g; }
+
+}  // extern "C"

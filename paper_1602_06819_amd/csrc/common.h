@@ -1,0 +1,126 @@
+// Device helpers shared by the gfx950 kernels of the k-nn graph builder.
+//
+// Keys.  Every ranking in the method uses the order (distance, id) with ties
+// going to the smaller id.  Distances here are non-negative (int32 squared
+// distances of uint8 points, or non-negative float32), so their 32-bit
+// patterns order like the values, and a candidate is packed into one 64-bit
+// key  (distance bits << 32) | id  whose unsigned order is exactly that
+// lexicographic order.  KEY_INF (all ones) marks an empty slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knng {
+
+constexpr int WAVE = 64;
+constexpr uint64_t KEY_INF = ~0ull;
+constexpr int32_t DIST_PAD_I32 = 0x7fffffff;
+
+__device__ __forceinline__ uint64_t make_key(uint32_t dbits, int32_t id) {
+  return ((uint64_t)dbits << 32) | (uint32_t)id;
+}
+__device__ __forceinline__ uint32_t key_dist(uint64_t key) { return (uint32_t)(key >> 32); }
+__device__ __forceinline__ int32_t key_id(uint64_t key) { return (int32_t)(uint32_t)key; }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---- cross-lane moves (ds_bpermute based) ----------------------------------
+__device__ __forceinline__ int shfl_i32(int v, int src) { return __shfl(v, src, WAVE); }
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
+  return (uint32_t)__shfl((int)v, src, WAVE);
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask, WAVE);
+  uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int delta) {
+  uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, delta, WAVE);
+  uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), delta, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ballot over the whole wave (64-bit mask)
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+  return __popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+__device__ __forceinline__ uint64_t min_u64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// ---- a top-k list spread over lanes: lane j < k holds the j-th smallest --
+// Inserts `cand` (uniform across the wave) if it beats the current k-th.
+__device__ __forceinline__ void lanes_topk_insert(uint64_t& mine, uint64_t cand, int k) {
+  const int lane = lane_id();
+  uint64_t kth = shfl_u64(mine, k - 1);
+  if (cand >= kth) return;
+  int pos = __popcll(ballot(lane < k && mine < cand));
+  uint64_t up = shfl_up_u64(mine, 1);
+  if (lane < k) {
+    if (lane > pos) mine = up;
+    else if (lane == pos) mine = cand;
+  }
+}
+
+// Offer every flagged lane's key to the lane-held top-k list.
+__device__ __forceinline__ void lanes_topk_offer(uint64_t& mine, bool flag, uint64_t key, int k) {
+  uint64_t kth = shfl_u64(mine, k - 1);
+  uint64_t pass = ballot(flag && key < kth);
+  while (pass) {
+    int j = __ffsll((long long)pass) - 1;
+    pass &= pass - 1;
+    uint64_t cand = shfl_u64(key, j);
+    lanes_topk_insert(mine, cand, k);
+  }
+}
+
+// ---- register lists: KM keys sorted ascending, compile-time indexed -------
+template <int KM>
+__device__ __forceinline__ void reg_list_insert(uint64_t (&L)[KM], uint64_t cand) {
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    uint64_t lo = min_u64(L[j], cand);
+    cand = max_u64(L[j], cand);
+    L[j] = lo;
+  }
+}
+
+// Merge two ascending lists, keeping the KM smallest in L (ascending).
+// min(a[j], b[KM-1-j]) is bitonic and holds the KM smallest; a bitonic
+// merge network then sorts it.
+template <int KM>
+__device__ __forceinline__ void reg_list_merge(uint64_t (&L)[KM], const uint64_t (&B)[KM]) {
+#pragma unroll
+  for (int j = 0; j < KM; ++j) L[j] = min_u64(L[j], B[KM - 1 - j]);
+#pragma unroll
+  for (int s = KM / 2; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if ((j & s) == 0) {
+        uint64_t a = L[j], b = L[j + s];
+        L[j] = min_u64(a, b);
+        L[j + s] = max_u64(a, b);
+      }
+    }
+  }
+}
+
+// Merge this lane's list with the list of lane (lane ^ mask).
+template <int KM>
+__device__ __forceinline__ void reg_list_merge_xor(uint64_t (&L)[KM], int mask) {
+  uint64_t other[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) other[j] = shfl_xor_u64(L[j], mask);
+  reg_list_merge<KM>(L, other);
+}
+
+}  // namespace knng

@@ -1,0 +1,112 @@
+// Ingest and small data-movement kernels.
+//
+// Ingest of uint8 points: a coordinate x in [0, 255] is stored as the int8
+// value x - 128.  Squared Euclidean distance is invariant under a common
+// shift, so distances computed on the shifted rows are the exact integer
+// distances of the original points, and the rows feed int8 dot-product and
+// int8 MFMA instructions directly.  Rows are zero padded to row_bytes (a
+// multiple of 16); padding contributes nothing to any distance.  The row's
+// squared norm (an int32: at most 4096 * 128^2) is stored beside it.
+#include "common.h"
+#include "internal.h"
+
+namespace knng {
+
+// One wave per row; each lane converts 4 coordinates at a time.
+__global__ __launch_bounds__(256) void k_ingest_u8(IngestArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.m) return;
+  const uint8_t* src = a.x + row * a.dim;
+  int8_t* dst = a.dst + row * a.row_bytes;
+  int acc = 0;
+  for (int c = lane * 4; c < a.row_bytes; c += 256) {
+    int packed = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int j = c + t;
+      int v = (j < a.dim) ? ((int)src[j] - 128) : 0;
+      packed |= (v & 0xff) << (8 * t);
+    }
+    *reinterpret_cast<int*>(dst + c) = packed;
+    acc = __builtin_amdgcn_sdot4(packed, packed, acc, false);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) a.norms[row] = acc;
+}
+
+hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.m + 3) / 4));
+  hipLaunchKernelGGL(k_ingest_u8, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+// Copy k entries per row between list arrays of different strides; entries
+// k .. dst_stride-1 of the destination are set to padding.  An id outside
+// [0, id_limit) becomes a padding entry, so lists supplied by a caller can
+// never make a kernel read outside the graph.
+__global__ void k_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
+                             int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
+                             int k, int64_t id_limit) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = rows * dst_stride;
+  if (i >= total) return;
+  int64_t r = i / dst_stride;
+  int j = (int)(i - r * dst_stride);
+  if (j < k) {
+    int32_t id = src_ids ? src_ids[r * src_stride + j] : -1;
+    bool ok = id >= 0 && (int64_t)id < id_limit;
+    if (dst_ids) dst_ids[i] = ok ? id : -1;
+    if (dst_d) dst_d[i] = (ok && src_d) ? src_d[r * src_stride + j] : DIST_PAD_I32;
+  } else {
+    if (dst_ids) dst_ids[i] = -1;
+    if (dst_d) dst_d[i] = DIST_PAD_I32;
+  }
+}
+
+hipError_t launch_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
+                             int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
+                             int k, int64_t id_limit, hipStream_t s) {
+  int64_t total = rows * dst_stride;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_lists, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     src_ids, src_d, src_stride, dst_ids, dst_d, dst_stride, rows, k, id_limit);
+  return hipGetLastError();
+}
+
+// int8 rows back to uint8 points (x + 128), dropping the padding.
+__global__ void k_export_u8(const int8_t* vec, int row_bytes, int dim, int64_t rows,
+                            uint8_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * dim) return;
+  int64_t r = i / dim;
+  int j = (int)(i - r * dim);
+  out[i] = (uint8_t)((int)vec[r * row_bytes + j] + 128);
+}
+
+hipError_t launch_export_u8(const int8_t* vec, int row_bytes, int dim, int64_t rows,
+                            uint8_t* out, hipStream_t s) {
+  int64_t total = rows * dim;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_u8, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vec,
+                     row_bytes, dim, rows, out);
+  return hipGetLastError();
+}
+
+}  // namespace knng

@@ -1,0 +1,210 @@
+"""Python front end of the library: a k-nn graph resident in GPU memory.
+
+PyTorch provides the device memory (storage, workspace, inputs, outputs)
+and the stream; every call goes through the C ABI of include/knng.h.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import check, knng_params
+
+_DTYPES = {"u8": _lib.KNNG_U8, "f32": _lib.KNNG_F32}
+_SCORES = {"exact": _lib.KNNG_SCORE_EXACT, "bf16": _lib.KNNG_SCORE_BF16,
+           "fp8": _lib.KNNG_SCORE_FP8}
+
+
+@dataclass(frozen=True)
+class GraphConfig:
+    dim: int
+    k: int
+    capacity: int
+    max_batch: int
+    speedup: int = 10
+    expansion_num: int = 5
+    expansion_den: int = 1
+    depth: int = 2
+    seed: int = 0x5EED
+    dtype: str = "u8"
+    score: str = "exact"
+
+    def params(self) -> knng_params:
+        return knng_params(dim=self.dim, k=self.k, dtype=_DTYPES[self.dtype],
+                           score=_SCORES[self.score], capacity=self.capacity,
+                           max_batch=self.max_batch, speedup=self.speedup,
+                           expansion_num=self.expansion_num, expansion_den=self.expansion_den,
+                           depth=self.depth, seed=self.seed)
+
+
+def storage_bytes(cfg: GraphConfig) -> int:
+    p = cfg.params()
+    n = _lib.lib.knng_storage_bytes(ctypes.byref(p))
+    if n == 0:
+        raise _lib.KnngError(_lib.KNNG_EINVAL, _lib.last_error())
+    return n
+
+
+def workspace_bytes(cfg: GraphConfig) -> int:
+    p = cfg.params()
+    n = _lib.lib.knng_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise _lib.KnngError(_lib.KNNG_EINVAL, _lib.last_error())
+    return n
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _aligned_buffer(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+class KnnGraph:
+    """A growing k-nn graph on one GPU.
+
+    Create it with :meth:`build_exact` (brute-force initial graph) or
+    :meth:`load` (points and lists supplied), then :meth:`insert` batches
+    and :meth:`query` read-only k-nn searches.
+    """
+
+    def __init__(self, cfg: GraphConfig, device="cuda"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.storage = _aligned_buffer(storage_bytes(cfg), self.device)
+        self.workspace = _aligned_buffer(workspace_bytes(cfg), self.device)
+        self._h = ctypes.c_void_p(None)
+
+    # -- construction ---------------------------------------------------------
+    @classmethod
+    def build_exact(cls, cfg: GraphConfig, x: torch.Tensor, stream=None) -> "KnnGraph":
+        g = cls(cfg, x.device)
+        x = g._as_points(x)
+        p = cfg.params()
+        check(_lib.lib.knng_build_exact(ctypes.byref(p), _ptr(x), x.shape[0], _ptr(g.storage),
+                                        g.storage.numel(), _ptr(g.workspace),
+                                        g.workspace.numel(), _stream(stream),
+                                        ctypes.byref(g._h)))
+        g._keep = x
+        return g
+
+    @classmethod
+    def load(cls, cfg: GraphConfig, x: torch.Tensor, ids: torch.Tensor, d: torch.Tensor,
+             stream=None) -> "KnnGraph":
+        g = cls(cfg, x.device)
+        x = g._as_points(x)
+        ids = ids.to(device=g.device, dtype=torch.int32).contiguous()
+        d = d.to(device=g.device, dtype=torch.int32 if cfg.dtype == "u8" else torch.float32)
+        d = d.contiguous()
+        if ids.shape != (x.shape[0], cfg.k) or d.shape != ids.shape:
+            raise ValueError("ids and d must have shape [n, k]")
+        p = cfg.params()
+        check(_lib.lib.knng_load(ctypes.byref(p), _ptr(x), x.shape[0], _ptr(ids), _ptr(d),
+                                 _ptr(g.storage), g.storage.numel(), _ptr(g.workspace),
+                                 g.workspace.numel(), _stream(stream), ctypes.byref(g._h)))
+        g._keep = (x, ids, d)
+        return g
+
+    def close(self) -> None:
+        """Free the handle (the device buffers are released with this object)."""
+        h = getattr(self, "_h", None)
+        lib = getattr(_lib, "lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.knng_destroy(h)
+        self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def _as_points(self, x: torch.Tensor) -> torch.Tensor:
+        want = torch.uint8 if self.cfg.dtype == "u8" else torch.float32
+        if x.dtype != want:
+            raise TypeError(f"points must be {want}, got {x.dtype}")
+        if x.dim() != 2 or x.shape[1] != self.cfg.dim:
+            raise ValueError(f"points must have shape [m, {self.cfg.dim}]")
+        return x.to(self.device).contiguous()
+
+    def _dist_dtype(self):
+        return torch.int32 if self.cfg.dtype == "u8" else torch.float32
+
+    @property
+    def n(self) -> int:
+        return int(_lib.lib.knng_size(self._h))
+
+    @property
+    def query_count(self) -> int:
+        return int(_lib.lib.knng_query_count(self._h))
+
+    # -- operations ------------------------------------------------------------
+    def insert(self, x: torch.Tensor, sims: bool = True, stream=None):
+        """Insert a batch; returns (first id, per-point similarity counts or None)."""
+        x = self._as_points(x)
+        out = torch.empty(x.shape[0], dtype=torch.int32, device=self.device) if sims else None
+        first = ctypes.c_int64(0)
+        check(_lib.lib.knng_insert_batch(self._h, _ptr(x), x.shape[0], ctypes.byref(first),
+                                         _ptr(out), _stream(stream)))
+        return first.value, out
+
+    def search(self, q: torch.Tensor, keys: torch.Tensor, trace: bool = False, stream=None):
+        """Raw iGNNS with explicit restart keys; returns (ids, d, evals, trace)."""
+        q = self._as_points(q)
+        m = q.shape[0]
+        keys = keys.to(device=self.device, dtype=torch.int64).contiguous()
+        ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
+        d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
+        ev = torch.empty(m, dtype=torch.int32, device=self.device)
+        tr = None
+        stride = 0
+        if trace:
+            stride = self.budget()
+            tr = torch.full((m, stride), -1, dtype=torch.int32, device=self.device)
+        check(_lib.lib.knng_search(self._h, _ptr(q), m, _ptr(keys), _ptr(ids), _ptr(d), _ptr(ev),
+                                   _ptr(tr), stride, _stream(stream)))
+        return ids, d, ev, tr
+
+    def query(self, q: torch.Tensor, stream=None):
+        """Read-only k-nn query; returns (ids, d, evals)."""
+        q = self._as_points(q)
+        m = q.shape[0]
+        ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
+        d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
+        ev = torch.empty(m, dtype=torch.int32, device=self.device)
+        check(_lib.lib.knng_query(self._h, _ptr(q), m, _ptr(ids), _ptr(d), _ptr(ev),
+                                  _stream(stream)))
+        return ids, d, ev
+
+    def lists(self, first: int = 0, count: int | None = None, stream=None):
+        count = self.n - first if count is None else count
+        ids = torch.empty((count, self.cfg.k), dtype=torch.int32, device=self.device)
+        d = torch.empty((count, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
+        check(_lib.lib.knng_get_lists(self._h, first, count, _ptr(ids), _ptr(d), _stream(stream)))
+        return ids, d
+
+    def points(self, first: int = 0, count: int | None = None, stream=None):
+        count = self.n - first if count is None else count
+        want = torch.uint8 if self.cfg.dtype == "u8" else torch.float32
+        x = torch.empty((count, self.cfg.dim), dtype=want, device=self.device)
+        check(_lib.lib.knng_get_points(self._h, first, count, _ptr(x), _stream(stream)))
+        return x
+
+    def budget(self, n: int | None = None) -> int:
+        n = self.n if n is None else n
+        b = -(-n // self.cfg.speedup)
+        return min(n, max(self.cfg.k, b))

@@ -55,6 +55,18 @@ typedef enum {
 } knng_status;
 
 typedef enum { KNNG_U8 = 0, KNNG_F32 = 1 } knng_dtype;
+
+/* Stages timed by knng_timing_* (one HIP event pair per launch). */
+typedef enum {
+  KNNG_STAGE_INGEST = 0,  /* points -> stored rows                          */
+  KNNG_STAGE_EXACT = 1,   /* brute-force tiles (knng_build_exact)           */
+  KNNG_STAGE_SEARCH = 2,  /* iGNNS of the points of an insert batch         */
+  KNNG_STAGE_PEERS = 3,   /* lists of the new nodes (search result + batch) */
+  KNNG_STAGE_UPDATE = 4,  /* update proposals (Algorithm 2)                 */
+  KNNG_STAGE_MERGE = 5,   /* proposals merged into the lists               */
+  KNNG_STAGE_QUERY = 6,   /* iGNNS of knng_search / knng_query              */
+  KNNG_NUM_STAGES = 7
+} knng_stage;
 typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } knng_score;
 
 /*
@@ -73,7 +85,10 @@ typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } k
  *             restart node r is discarded iff
  *             den * (1 + d_r) > num * (1 + d_best), i.e. similarity
  *             1 / (1 + d) below s_max / e.
- *  depth      DEPTH of the Update procedure (Algorithm 2): 1 or 2.
+ *  depth      DEPTH of the Update procedure (Algorithm 2), 1 .. 8, such
+ *             that the per-point processed set (2 (k + ... + k^depth) slots)
+ *             and two level arrays (k^(depth-1) slots each) fit in 64 KiB.
+ *             Supported: k = 10 up to depth 3, k = 50 up to depth 2.
  *  seed       seed of the restart permutations (see knng_search).
  */
 typedef struct {
@@ -137,14 +152,15 @@ knng_status knng_load(const knng_params* params, const void* x_dev, int64_t n,
  *  keys_dev   [m] uint64 restart keys, device (an insert uses its new id).
  *  ids_dev    [m][k] int32 out;  d_dev [m][k] int32 / float out.
  *  evals_dev  [m] int32 out (distance evaluations), or NULL.
+ *  list_reads_dev [m] int32 out (adjacency lists read by the climb), or NULL.
  *  trace_dev  [m][trace_stride] int32 out: evaluated ids in evaluation
  *             order, -1 after the last; or NULL.  trace_stride >= B(n).
  * Read-only with respect to the graph.  m <= max_batch.
  */
 knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
                         const uint64_t* keys_dev, int32_t* ids_dev, void* d_dev,
-                        int32_t* evals_dev, int32_t* trace_dev, int64_t trace_stride,
-                        hipStream_t stream);
+                        int32_t* evals_dev, int32_t* list_reads_dev, int32_t* trace_dev,
+                        int64_t trace_stride, hipStream_t stream);
 
 /*
  * Insert a batch of b points (Algorithms 1 and 2, batch form).  With n the
@@ -162,21 +178,25 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
  *  first_id_host  out: n (ids are first_id .. first_id + b - 1), or NULL.
  *  sims_dev       [b] int32 out: similarities spent per point (search
  *                 evaluations + (b - 1) peers + update evaluations), or NULL.
+ *  stats_dev      [b][3] int32 out: per point (search evaluations,
+ *                 adjacency lists read by the search, update evaluations),
+ *                 or NULL.
  * Needs n + b <= capacity (KNNG_ECAPACITY otherwise) and b <= max_batch.
  */
 knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
                               int64_t* first_id_host, int32_t* sims_dev,
-                              hipStream_t stream);
+                              int32_t* stats_dev, hipStream_t stream);
 
 /*
  * Read-only k-nn query of m points on the current graph: iGNNS with the
  * keys 2^62 + s, where s counts every query this handle has answered
  * before (the first query of a handle has s = 0).
- *  ids_dev [m][k] int32, d_dev [m][k] int32/float, evals_dev [m] or NULL.
+ *  ids_dev [m][k] int32, d_dev [m][k] int32/float, evals_dev and
+ *  list_reads_dev [m] int32 (as for knng_search) or NULL.
  */
 knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m,
                        int32_t* ids_dev, void* d_dev, int32_t* evals_dev,
-                       hipStream_t stream);
+                       int32_t* list_reads_dev, hipStream_t stream);
 
 /* Copy lists of nodes [first, first + count) out: ids_dev [count][k] int32,
  * d_dev [count][k] int32/float (either may be NULL). */
@@ -186,6 +206,15 @@ knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,
 /* Copy points [first, first + count) out as [count][dim] in the input dtype. */
 knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count,
                             void* x_dev, hipStream_t stream);
+
+/* Stage timing.  knng_timing_enable(g, 1) clears the accumulated times and
+ * from then on records a HIP event pair on the call's stream around every
+ * launch of each stage; knng_timing_enable(g, 0) stops recording.
+ * knng_timing_read waits for the recorded events and returns, per stage,
+ * the summed GPU milliseconds (ms_host[KNNG_NUM_STAGES]) and the number of
+ * launches (launches_host[KNNG_NUM_STAGES]); either pointer may be NULL. */
+knng_status knng_timing_enable(knng_graph* g, int enable);
+knng_status knng_timing_read(knng_graph* g, double* ms_host, int64_t* launches_host);
 
 /* Number of nodes (counting every insert already enqueued). */
 int64_t knng_size(const knng_graph* g);

@@ -73,11 +73,14 @@ def exact_graph_loops(X: np.ndarray, k: int):
 
 
 def _chunk_distances(Xf: np.ndarray, norms: np.ndarray, lo: int, hi: int) -> np.ndarray:
-    G = Xf[lo:hi] @ Xf.T
-    return norms[lo:hi, None] + norms[None, :] - 2.0 * G
+    D = Xf[lo:hi] @ Xf.T
+    D *= -2.0
+    D += norms[None, :]
+    D += norms[lo:hi, None]
+    return D
 
 
-def exact_graph(X: np.ndarray, k: int, chunk: int = 1024, threads: int | None = None):
+def exact_graph(X: np.ndarray, k: int, chunk: int = 512, threads: int | None = None):
     """Exact k-nn graph of all rows of X; returns (ids [n,k], dist [n,k])."""
     n = X.shape[0]
     ids, dist = empty_lists(n, k, X.dtype)
@@ -94,32 +97,31 @@ def exact_graph(X: np.ndarray, k: int, chunk: int = 1024, threads: int | None = 
     for lo in range(0, n, chunk):
         hi = min(n, lo + chunk)
         D = _chunk_distances(Xf, norms, lo, hi)
-        if is_int:
-            D = np.rint(D)                     # exact integers already
         rows = np.arange(hi - lo)
         D[rows, lo + rows] = np.inf            # exclude self
-        Dt = torch.from_numpy(D)
-        vals, idx = torch.topk(Dt, m, dim=1, largest=False, sorted=True)
+        vals, idx = torch.topk(torch.from_numpy(D), m, dim=1, largest=False, sorted=True)
         vals = vals.numpy()
-        idx = idx.numpy()
-        for r in range(hi - lo):
-            u = lo + r
-            if is_int:
-                cand_ok = m == n - 1 or vals[r, m - 1] > vals[r, kk - 1]
-                if cand_ok:
-                    cd = vals[r].astype(np.int64)
-                    cv = idx[r].astype(np.int64)
-                    sel = cd <= cd[kk - 1]
-                    cd, cv = cd[sel], cv[sel]
-                    o = np.lexsort((cv, cd))[:kk]
-                    pairs = [(int(cd[j]), int(cv[j])) for j in o]
-                else:
-                    pairs = exact_row(X, u, kk)
-            else:
+        idx = idx.numpy().astype(np.int64)
+        if is_int:
+            # uint8 data: D holds exact integers.  Order the m candidates of
+            # each row by (distance, id) through one int64 key per entry.
+            key = (vals.astype(np.int64) << 31) | idx
+            key.sort(axis=1)
+            ok = np.full(hi - lo, m == n - 1) | (vals[:, m - 1] > vals[:, kk - 1])
+            ids[lo:hi, :kk] = np.where(ok[:, None], key[:, :kk] & ((1 << 31) - 1), -1)
+            dist[lo:hi, :kk] = np.where(ok[:, None], key[:, :kk] >> 31, dist[lo:hi, :kk])
+            for r in np.nonzero(~ok)[0]:
+                # candidate set not provably complete (ties at the k-th): full row
+                for j, (d, v) in enumerate(exact_row(X, lo + int(r), kk)):
+                    ids[lo + r, j] = v
+                    dist[lo + r, j] = d
+        else:
+            for r in range(hi - lo):
+                u = lo + r
                 pairs = _float_row(X, u, kk, vals[r], idx[r], m, n, norms[u], max_norm)
-            for j, (d, v) in enumerate(pairs):
-                ids[u, j] = v
-                dist[u, j] = d
+                for j, (d, v) in enumerate(pairs):
+                    ids[u, j] = v
+                    dist[u, j] = d
     return ids, dist
 
 

@@ -24,7 +24,10 @@ EXPORTED = [
     "knng_storage_bytes", "knng_workspace_bytes", "knng_build_exact", "knng_load",
     "knng_search", "knng_insert_batch", "knng_query", "knng_get_lists", "knng_get_points",
     "knng_size", "knng_query_count", "knng_last_error", "knng_destroy",
+    "knng_timing_enable", "knng_timing_read",
 ]
+
+STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
 
 
 class knng_params(ctypes.Structure):
@@ -68,11 +71,11 @@ def _load() -> ctypes.CDLL:
     lib.knng_load.argtypes = [P(knng_params), vp, i64, vp, vp, vp, ctypes.c_size_t, vp,
                               ctypes.c_size_t, vp, P(vp)]
     lib.knng_load.restype = ctypes.c_int
-    lib.knng_search.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i64, vp]
+    lib.knng_search.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, i64, vp]
     lib.knng_search.restype = ctypes.c_int
-    lib.knng_insert_batch.argtypes = [vp, vp, i64, P(i64), vp, vp]
+    lib.knng_insert_batch.argtypes = [vp, vp, i64, P(i64), vp, vp, vp]
     lib.knng_insert_batch.restype = ctypes.c_int
-    lib.knng_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.knng_query.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     lib.knng_query.restype = ctypes.c_int
     lib.knng_get_lists.argtypes = [vp, i64, i64, vp, vp, vp]
     lib.knng_get_lists.restype = ctypes.c_int
@@ -86,6 +89,10 @@ def _load() -> ctypes.CDLL:
     lib.knng_last_error.restype = ctypes.c_char_p
     lib.knng_destroy.argtypes = [vp]
     lib.knng_destroy.restype = None
+    lib.knng_timing_enable.argtypes = [vp, ctypes.c_int]
+    lib.knng_timing_enable.restype = ctypes.c_int
+    lib.knng_timing_read.argtypes = [vp, P(ctypes.c_double), P(i64)]
+    lib.knng_timing_read.restype = ctypes.c_int
     return lib
 
 

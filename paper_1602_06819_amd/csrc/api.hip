@@ -7,12 +7,43 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 #include "internal.h"
 #include "knng.h"
 
 using namespace knng;
+
+// Opt-in stage timing: a pair of HIP events recorded on the caller's
+// stream around every launch of a stage; read back (and summed) on demand.
+struct StageTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KNNG_NUM_STAGES];
+  std::vector<hipEvent_t> pool;
+  double ms[KNNG_NUM_STAGES] = {};
+  int64_t launches[KNNG_NUM_STAGES] = {};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~StageTimer() {
+    for (auto& v : pending)
+      for (auto& pr : v) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+      }
+    for (auto e : pool) hipEventDestroy(e);
+  }
+};
 
 struct knng_graph {
   knng_params p;
@@ -24,6 +55,7 @@ struct knng_graph {
   size_t ws_bytes;
   int64_t n;
   int64_t qcount;
+  StageTimer timer;
 };
 
 namespace {
@@ -56,6 +88,34 @@ knng_status dev(hipError_t e, const char* what) {
     if (_s != KNNG_OK) return _s;                 \
   } while (0)
 
+// Records start/stop events around the launches of one stage when timing
+// is on.
+class Timed {
+ public:
+  Timed(knng_graph* g, int stage, hipStream_t s) : g_(g), stage_(stage), s_(s) {
+    if (g_ && g_->timer.on) {
+      start_ = g_->timer.get();
+      stop_ = g_->timer.get();
+      if (start_ && stop_) hipEventRecord(start_, s_);
+    }
+  }
+  ~Timed() {
+    if (start_ && stop_) {
+      hipEventRecord(stop_, s_);
+      g_->timer.pending[stage_].push_back({start_, stop_});
+    } else {
+      if (start_) g_->timer.pool.push_back(start_);
+      if (stop_) g_->timer.pool.push_back(stop_);
+    }
+  }
+
+ private:
+  knng_graph* g_;
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+};
+
 constexpr size_t ALIGN = 256;
 constexpr int64_t PARTIAL_LISTS = 32768;
 constexpr int64_t QUERY_KEY_BASE = (int64_t)1 << 62;
@@ -67,6 +127,31 @@ size_t take(size_t& cur, size_t bytes) {
 }
 
 int k_pad_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+// Update sizes for DEPTH levels: at most k + k^2 + ... + k^depth processed
+// nodes per new point; the processed set keeps at most half its slots full;
+// a level array holds the largest level that is expanded (k^(depth-1)).
+struct UpdateSizes {
+  int64_t props_per_point = 0;
+  int64_t hash_cap = 0;
+  int64_t front_cap = 0;
+  int64_t lds_bytes() const { return (hash_cap + 2 * front_cap) * 4; }
+};
+
+UpdateSizes update_sizes(int k, int depth) {
+  UpdateSizes u;
+  int64_t level = 1;
+  for (int l = 1; l <= depth; ++l) {
+    level *= k;
+    u.props_per_point += level;
+    if (l == depth - 1) u.front_cap = level;
+    if (u.props_per_point > (1 << 24)) break;
+  }
+  if (u.front_cap < k) u.front_cap = k;
+  u.hash_cap = 64;
+  while (u.hash_cap < 2 * u.props_per_point) u.hash_cap <<= 1;
+  return u;
+}
 
 knng_status check_params(const knng_params* p) {
   if (!p) return fail(KNNG_EINVAL, "params is NULL");
@@ -87,7 +172,10 @@ knng_status check_params(const knng_params* p) {
   if (p->speedup < 1) return fail(KNNG_EINVAL, "speedup must be >= 1");
   if (p->expansion_den < 1 || p->expansion_num <= p->expansion_den)
     return fail(KNNG_EINVAL, "expansion num/den must be > 1 with den >= 1");
-  if (p->depth < 1 || p->depth > 2) return fail(KNNG_EINVAL, "depth must be 1 or 2");
+  if (p->depth < 1 || p->depth > 8) return fail(KNNG_EINVAL, "depth must be 1 .. 8");
+  if (update_sizes(p->k, p->depth).lds_bytes() > 65536)
+    return fail(KNNG_EINVAL, "depth %d with k %d needs more than 64 KiB of LDS per update "
+                             "wavefront (k^depth too large)", p->depth, p->k);
   return KNNG_OK;
 }
 
@@ -111,7 +199,7 @@ StorageLayout storage_layout(const knng_params& p) {
 WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   WorkspaceLayout W;
   W.M = p.max_batch;
-  W.props_per_point = (int64_t)p.k + (int64_t)p.k * p.k;
+  W.props_per_point = update_sizes(p.k, p.depth).props_per_point;
   W.partial_lists = PARTIAL_LISTS;
   size_t cur = 0;
   const size_t M = (size_t)W.M;
@@ -121,6 +209,7 @@ WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   W.off_res_d = take(cur, M * S.k_pad * 4);
   W.off_evals = take(cur, M * 4);
   W.off_upd = take(cur, M * 4);
+  W.off_lreads = take(cur, M * 4);
   W.off_props = take(cur, M * (size_t)W.props_per_point * sizeof(Proposal));
   W.off_touched = take(cur, M * (size_t)W.props_per_point * 4);
   W.off_counters = take(cur, 256);
@@ -185,8 +274,8 @@ knng_status make_handle(const knng_params* p, void* storage, size_t storage_byte
 // Search m ingested query rows (at qvec/qnorm) on the current graph.
 knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, int64_t m,
                        const uint64_t* keys, uint64_t key_base, int32_t* out_ids,
-                       int32_t* out_d, int out_stride, int32_t* evals, int32_t* trace,
-                       int64_t trace_stride, hipStream_t stream) {
+                       int32_t* out_d, int out_stride, int32_t* evals, int32_t* list_reads,
+                       int32_t* trace, int64_t trace_stride, int stage, hipStream_t stream) {
   const StorageLayout& S = g->S;
   SearchArgs a{};
   a.vec = at<int8_t>(g->st, S.off_vec);
@@ -209,12 +298,14 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, 
   a.out_d = out_d;
   a.out_stride = out_stride;
   a.out_evals = evals;
+  a.out_list_reads = list_reads;
   a.trace = trace;
   a.trace_stride = trace_stride;
   a.vis_words = (int32_t)((g->n + 31) / 32);
   if ((size_t)a.vis_words * 4 > 65536)
     return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
                              "which this build does not provide");
+  Timed t(g, stage, stream);
   KNNG_TRY(launch_search_u8(a, stream), "search launch");
   return KNNG_OK;
 }
@@ -228,6 +319,7 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int8_t* dst, int32_t
   a.m = m;
   a.dim = g->S.dim;
   a.row_bytes = g->S.row_bytes;
+  Timed t(g, KNNG_STAGE_INGEST, stream);
   KNNG_TRY(launch_ingest_u8(a, stream), "ingest launch");
   return KNNG_OK;
 }
@@ -352,8 +444,9 @@ knng_status knng_load(const knng_params* p, const void* x_dev, int64_t n, const 
 }
 
 knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint64_t* keys_dev,
-                        int32_t* ids_dev, void* d_dev, int32_t* evals_dev, int32_t* trace_dev,
-                        int64_t trace_stride, hipStream_t stream) {
+                        int32_t* ids_dev, void* d_dev, int32_t* evals_dev,
+                        int32_t* list_reads_dev, int32_t* trace_dev, int64_t trace_stride,
+                        hipStream_t stream) {
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (m == 0) return ok();
@@ -376,13 +469,14 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
   if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
   s = run_search(g, qv, qn, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
-                 trace_dev, trace_stride, stream);
+                 list_reads_dev, trace_dev, trace_stride, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   return ok();
 }
 
 knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids_dev,
-                       void* d_dev, int32_t* evals_dev, hipStream_t stream) {
+                       void* d_dev, int32_t* evals_dev, int32_t* list_reads_dev,
+                       hipStream_t stream) {
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (m == 0) return ok();
@@ -401,14 +495,16 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids
   int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
   if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
   s = run_search(g, qv, qn, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
-                 (int32_t*)d_dev, g->S.k, evals_dev, nullptr, 0, stream);
+                 (int32_t*)d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0,
+                 KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   g->qcount += m;
   return ok();
 }
 
 knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
-                              int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream) {
+                              int64_t* first_id_host, int32_t* sims_dev, int32_t* stats_dev,
+                              hipStream_t stream) {
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (b == 0) {
@@ -437,6 +533,7 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   int32_t* res_ids = at<int32_t>(g->ws, W.off_res_ids);
   int32_t* res_d = at<int32_t>(g->ws, W.off_res_d);
   int32_t* evals = at<int32_t>(g->ws, W.off_evals);
+  int32_t* lreads = at<int32_t>(g->ws, W.off_lreads);
   int32_t* counters = at<int32_t>(g->ws, W.off_counters);
   int8_t* bvec = vec + n * S.row_bytes;
   int32_t* bnorm = norms + n;
@@ -446,7 +543,7 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   if ((s = ingest(g, x_dev, b, bvec, bnorm, stream)) != KNNG_OK) return s;
   // (i) iGNNS of every new point on the pre-batch graph, key = its id
   s = run_search(g, bvec, bnorm, b, nullptr, (uint64_t)n, res_ids, res_d, S.k_pad, evals,
-                 nullptr, 0, stream);
+                 lreads, nullptr, 0, KNNG_STAGE_SEARCH, stream);
   if (s != KNNG_OK) return s;
   // (ii) lists of the new nodes: search result + batch peers
   PeerArgs pa{};
@@ -461,7 +558,10 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   pa.res_d = res_d;
   pa.list_ids = ids + n * S.k_pad;
   pa.list_d = dist + n * S.k_pad;
-  KNNG_TRY(launch_peers_u8(pa, stream), "peers launch");
+  {
+    Timed t(g, KNNG_STAGE_PEERS, stream);
+    KNNG_TRY(launch_peers_u8(pa, stream), "peers launch");
+  }
   // (iii) update proposals on the pre-batch lists
   KNNG_TRY(launch_fill_i32(counters, 2, 0, stream), "fill");
   UpdateArgs ua{};
@@ -483,11 +583,16 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   ua.touched = at<int32_t>(g->ws, W.off_touched);
   ua.counters = counters;
   ua.evals = evals;
+  ua.list_reads = lreads;
   ua.sims = sims_dev;
-  int hc = 64;
-  while (hc < 2 * W.props_per_point) hc <<= 1;
-  ua.hash_cap = hc;
-  KNNG_TRY(launch_update_u8(ua, stream), "update launch");
+  ua.stats = stats_dev;
+  const UpdateSizes us = update_sizes(S.k, g->p.depth);
+  ua.hash_cap = (int)us.hash_cap;
+  ua.front_cap = (int)us.front_cap;
+  {
+    Timed t(g, KNNG_STAGE_UPDATE, stream);
+    KNNG_TRY(launch_update_u8(ua, stream), "update launch");
+  }
   // (iv) merge proposals into the pre-batch lists
   MergeArgs ma{};
   ma.nbr_ids = ids;
@@ -499,7 +604,10 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   ma.touched = ua.touched;
   ma.counters = counters;
   ma.max_touched = (int32_t)(b * W.props_per_point);
-  KNNG_TRY(launch_merge(ma, stream), "merge launch");
+  {
+    Timed t(g, KNNG_STAGE_MERGE, stream);
+    KNNG_TRY(launch_merge(ma, stream), "merge launch");
+  }
   // (v)
   if (first_id_host) *first_id_host = n;
   g->n = n + b;
@@ -532,6 +640,43 @@ knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count, v
   KNNG_TRY(launch_export_u8(at<int8_t>(g->st, S.off_vec) + first * S.row_bytes, S.row_bytes,
                             S.dim, count, (uint8_t*)x_dev, stream),
            "export points");
+  return ok();
+}
+
+knng_status knng_timing_enable(knng_graph* g, int enable) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  StageTimer& T = g->timer;
+  for (int st = 0; st < KNNG_NUM_STAGES; ++st) {
+    for (auto& pr : T.pending[st]) {
+      hipEventSynchronize(pr.second);
+      T.pool.push_back(pr.first);
+      T.pool.push_back(pr.second);
+    }
+    T.pending[st].clear();
+    T.ms[st] = 0.0;
+    T.launches[st] = 0;
+  }
+  T.on = enable != 0;
+  return ok();
+}
+
+knng_status knng_timing_read(knng_graph* g, double* ms_host, int64_t* launches_host) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  StageTimer& T = g->timer;
+  for (int st = 0; st < KNNG_NUM_STAGES; ++st) {
+    for (auto& pr : T.pending[st]) {
+      KNNG_TRY(hipEventSynchronize(pr.second), "event synchronize");
+      float ms = 0.f;
+      KNNG_TRY(hipEventElapsedTime(&ms, pr.first, pr.second), "event elapsed time");
+      T.ms[st] += ms;
+      T.launches[st] += 1;
+      T.pool.push_back(pr.first);
+      T.pool.push_back(pr.second);
+    }
+    T.pending[st].clear();
+    if (ms_host) ms_host[st] = T.ms[st];
+    if (launches_host) launches_host[st] = T.launches[st];
+  }
   return ok();
 }
 

@@ -37,7 +37,7 @@ struct WorkspaceLayout {
   int64_t props_per_point = 0;
   int64_t partial_lists = 0;   // capacity in lists of k_pad keys
   size_t off_qvec = 0, off_qnorm = 0, off_res_ids = 0, off_res_d = 0, off_evals = 0,
-         off_upd = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
+         off_upd = 0, off_lreads = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
          off_keys = 0, total = 0;
 };
 
@@ -80,6 +80,7 @@ struct SearchArgs {
   const uint64_t* keys; uint64_t key_base;   // key = keys ? keys[i] : key_base + i
   int32_t* out_ids; int32_t* out_d; int out_stride;
   int32_t* out_evals;
+  int32_t* out_list_reads;   // neighbour lists read per query (may be null)
   int32_t* trace; int64_t trace_stride;
   int32_t vis_words;
 };
@@ -99,8 +100,11 @@ struct UpdateArgs {
   const int32_t* res_ids; const int32_t* res_d;
   int depth;
   Proposal* props; int32_t* touched; int32_t* counters;
-  const int32_t* evals; int32_t* sims;            // sims may be null
+  const int32_t* evals; const int32_t* list_reads;
+  int32_t* sims;                                  // may be null
+  int32_t* stats;                                 // [b][3] or null
   int hash_cap;          // processed-set slots (power of two)
+  int front_cap;         // slots of one level array (largest expanded level)
 };
 
 struct MergeArgs {

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(64) void k_search_u8(SearchArgs a) {
 
     uint64_t rk = KEY_INF;          // result list: lane j < k holds the j-th best
     int evals = 0;
+    int list_reads = 0;             // neighbour lists read by the climb
     uint32_t P = 0;                 // permutation positions consumed
     uint32_t xP = lcg.x0;           // value at position P
     int32_t cur = -1, dcur = 0;
@@ -192,6 +193,7 @@ __global__ __launch_bounds__(64) void k_search_u8(SearchArgs a) {
         cid = lane < a.k ? a.nbr_ids[(int64_t)cur * a.k_pad + lane] : -1;
         valid = cid >= 0 && !vis_test(vis, cid >= 0 ? cid : 0);
         cnt = a.k;
+        ++list_reads;
       }
       int32_t d = eval_rows<G, CPL>(a.vec, a.row_bytes, cid, valid, cnt, qc, qn);
 
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(64) void k_search_u8(SearchArgs a) {
     }
     if (lane == 0) {
       if (a.out_evals) a.out_evals[qi] = evals;
+      if (a.out_list_reads) a.out_list_reads[qi] = list_reads;
       if (a.trace && evals < a.trace_stride) a.trace[trace_base + evals] = -1;
     }
     __syncthreads();
@@ -336,9 +339,20 @@ __device__ __forceinline__ void emit_proposal(const UpdateArgs& a, int32_t u, in
   }
 }
 
+// One wavefront per new point.  Level 1 is the point's search result (its
+// distances are reused); level l + 1 is the union of the pre-batch lists of
+// the level-l nodes.  A per-point processed set (open addressing in LDS)
+// makes every node count once, whatever the order in which lanes reach it;
+// the level arrays live in LDS as well.  Each processed node gets the
+// proposal (node, distance, new id) if it beats the node's current k-th
+// entry -- the only case in which the merge can keep it.
 template <int G, int CPL>
 __global__ __launch_bounds__(64) void k_update_u8(UpdateArgs a) {
-  extern __shared__ int32_t setv[];
+  extern __shared__ int32_t lds[];
+  int32_t* setv = lds;                       // processed set, hash_cap slots
+  int32_t* front = lds + a.hash_cap;         // current level, front_cap slots
+  int32_t* nxt = front + a.front_cap;        // next level, front_cap slots
+  __shared__ int32_t next_count;
   const int lane = threadIdx.x;
   const int32_t i = blockIdx.x;
   if (i >= a.b) return;
@@ -352,11 +366,14 @@ __global__ __launch_bounds__(64) void k_update_u8(UpdateArgs a) {
     u = a.res_ids[(int64_t)i * a.k_pad + lane];
     du = a.res_d[(int64_t)i * a.k_pad + lane];
   }
-  if (u >= 0) {
+  bool fresh1 = u >= 0 && set_insert(setv, a.hash_cap, u);
+  if (fresh1) {
     int32_t thr = a.nbr_d[(int64_t)u * a.k_pad + a.k - 1];
     if (du < thr) emit_proposal(a, u, du, src);
-    set_insert(setv, a.hash_cap, u);
   }
+  uint64_t m1 = ballot(fresh1);
+  if (fresh1) front[rank_below(m1)] = u;
+  int fcount = __popcll(m1);
   __syncthreads();
 
   int upd = 0;
@@ -364,26 +381,54 @@ __global__ __launch_bounds__(64) void k_update_u8(UpdateArgs a) {
     v4i qc[CPL];
     load_query<G, CPL>(a.bvec + (int64_t)i * a.row_bytes, a.row_bytes, qc);
     const int32_t qn = a.bnorm[i];
-    const int total = a.k * a.k;
-    for (int c0 = 0; c0 < total; c0 += WAVE) {
-      int c = c0 + lane;
-      int t = c / a.k;
-      int s = c - t * a.k;
-      int32_t ut = shfl_i32(u, t < WAVE ? t : 0);
-      int32_t w = -1;
-      if (c < total && ut >= 0) w = a.nbr_ids[(int64_t)ut * a.k_pad + s];
-      bool fresh = w >= 0 && set_insert(setv, a.hash_cap, w);
+    for (int level = 2; level <= a.depth; ++level) {
+      const bool keep = level < a.depth;     // this level is expanded further
+      if (lane == 0) next_count = 0;
       __syncthreads();
-      int cnt = total - c0 < WAVE ? total - c0 : WAVE;
-      int32_t d = eval_rows<G, CPL>(a.vec, a.row_bytes, w, fresh, cnt, qc, qn);
-      if (fresh) {
-        int32_t thr = a.nbr_d[(int64_t)w * a.k_pad + a.k - 1];
-        if (d < thr) emit_proposal(a, w, d, src);
+      const int total = fcount * a.k;
+      for (int c0 = 0; c0 < total; c0 += WAVE) {
+        int c = c0 + lane;
+        int t = c / a.k;
+        int sidx = c - t * a.k;
+        int32_t w = -1;
+        if (c < total) {
+          int32_t ut = front[t];
+          w = a.nbr_ids[(int64_t)ut * a.k_pad + sidx];
+        }
+        bool fresh = w >= 0 && set_insert(setv, a.hash_cap, w);
+        __syncthreads();
+        int cnt = total - c0 < WAVE ? total - c0 : WAVE;
+        int32_t d = eval_rows<G, CPL>(a.vec, a.row_bytes, w, fresh, cnt, qc, qn);
+        if (fresh) {
+          int32_t thr = a.nbr_d[(int64_t)w * a.k_pad + a.k - 1];
+          if (d < thr) emit_proposal(a, w, d, src);
+        }
+        uint64_t mf = ballot(fresh);
+        upd += __popcll(mf);
+        if (keep) {
+          int base = next_count;
+          if (fresh && base + rank_below(mf) < a.front_cap) nxt[base + rank_below(mf)] = w;
+          __syncthreads();
+          if (lane == 0) next_count = base + __popcll(mf);
+          __syncthreads();
+        }
       }
-      upd += __popcll(ballot(fresh));
+      if (keep) {
+        __syncthreads();
+        fcount = next_count < a.front_cap ? next_count : a.front_cap;
+        for (int s2 = lane; s2 < fcount; s2 += WAVE) front[s2] = nxt[s2];
+        __syncthreads();
+      }
     }
   }
-  if (lane == 0 && a.sims) a.sims[i] = a.evals[i] + (a.b - 1) + upd;
+  if (lane == 0) {
+    if (a.sims) a.sims[i] = a.evals[i] + (a.b - 1) + upd;
+    if (a.stats) {
+      a.stats[3 * (int64_t)i + 0] = a.evals[i];
+      a.stats[3 * (int64_t)i + 1] = a.list_reads[i];
+      a.stats[3 * (int64_t)i + 2] = upd;
+    }
+  }
 }
 
 // ---- merge ----------------------------------------------------------------
@@ -463,7 +508,7 @@ hipError_t launch_peers_u8(const PeerArgs& a, hipStream_t s) {
 
 hipError_t launch_update_u8(const UpdateArgs& a, hipStream_t s) {
   if (a.b <= 0) return hipSuccess;
-  size_t lds = (size_t)a.hash_cap * 4;
+  size_t lds = ((size_t)a.hash_cap + 2 * (size_t)a.front_cap) * 4;
   return dispatch_rows<UpdateFn>(a.row_bytes, a, s, dim3((unsigned)a.b), lds);
 }
 

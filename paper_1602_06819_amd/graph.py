@@ -153,42 +153,66 @@ class KnnGraph:
         return int(_lib.lib.knng_query_count(self._h))
 
     # -- operations ------------------------------------------------------------
-    def insert(self, x: torch.Tensor, sims: bool = True, stream=None):
-        """Insert a batch; returns (first id, per-point similarity counts or None)."""
+    def insert(self, x: torch.Tensor, sims: bool = True, stats: bool = False, stream=None):
+        """Insert a batch; returns (first id, per-point similarity counts or
+        None) or, with ``stats``, (first id, sims, stats [b, 3] = search
+        evaluations, lists read by the search, update evaluations)."""
         x = self._as_points(x)
         out = torch.empty(x.shape[0], dtype=torch.int32, device=self.device) if sims else None
+        st = torch.empty((x.shape[0], 3), dtype=torch.int32, device=self.device) if stats else None
         first = ctypes.c_int64(0)
         check(_lib.lib.knng_insert_batch(self._h, _ptr(x), x.shape[0], ctypes.byref(first),
-                                         _ptr(out), _stream(stream)))
+                                         _ptr(out), _ptr(st), _stream(stream)))
+        if stats:
+            return first.value, out, st
         return first.value, out
 
-    def search(self, q: torch.Tensor, keys: torch.Tensor, trace: bool = False, stream=None):
-        """Raw iGNNS with explicit restart keys; returns (ids, d, evals, trace)."""
+    def search(self, q: torch.Tensor, keys: torch.Tensor, trace: bool = False,
+               list_reads: bool = False, stream=None):
+        """Raw iGNNS with explicit restart keys; returns (ids, d, evals, trace)
+        or, with ``list_reads``, (ids, d, evals, trace, list_reads)."""
         q = self._as_points(q)
         m = q.shape[0]
         keys = keys.to(device=self.device, dtype=torch.int64).contiguous()
         ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
         d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
         ev = torch.empty(m, dtype=torch.int32, device=self.device)
+        lr = torch.empty(m, dtype=torch.int32, device=self.device) if list_reads else None
         tr = None
         stride = 0
         if trace:
             stride = self.budget()
             tr = torch.full((m, stride), -1, dtype=torch.int32, device=self.device)
         check(_lib.lib.knng_search(self._h, _ptr(q), m, _ptr(keys), _ptr(ids), _ptr(d), _ptr(ev),
-                                   _ptr(tr), stride, _stream(stream)))
+                                   _ptr(lr), _ptr(tr), stride, _stream(stream)))
+        if list_reads:
+            return ids, d, ev, tr, lr
         return ids, d, ev, tr
 
-    def query(self, q: torch.Tensor, stream=None):
-        """Read-only k-nn query; returns (ids, d, evals)."""
+    def query(self, q: torch.Tensor, list_reads: bool = False, stream=None):
+        """Read-only k-nn query; returns (ids, d, evals[, list_reads])."""
         q = self._as_points(q)
         m = q.shape[0]
         ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
         d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
         ev = torch.empty(m, dtype=torch.int32, device=self.device)
-        check(_lib.lib.knng_query(self._h, _ptr(q), m, _ptr(ids), _ptr(d), _ptr(ev),
+        lr = torch.empty(m, dtype=torch.int32, device=self.device) if list_reads else None
+        check(_lib.lib.knng_query(self._h, _ptr(q), m, _ptr(ids), _ptr(d), _ptr(ev), _ptr(lr),
                                   _stream(stream)))
+        if list_reads:
+            return ids, d, ev, lr
         return ids, d, ev
+
+    def timing(self, enable: bool) -> None:
+        """Start (clearing earlier totals) or stop per-stage event timing."""
+        check(_lib.lib.knng_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self) -> dict:
+        """{stage: (total GPU ms, launches)} of the stages timed so far."""
+        ms = (ctypes.c_double * len(_lib.STAGES))()
+        cnt = (ctypes.c_int64 * len(_lib.STAGES))()
+        check(_lib.lib.knng_timing_read(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.STAGES)}
 
     def lists(self, first: int = 0, count: int | None = None, stream=None):
         count = self.n - first if count is None else count

@@ -52,7 +52,7 @@ def _p(L, **kw):
 
 
 @pytest.mark.parametrize("bad", [dict(k=0), dict(k=65), dict(dim=0), dict(speedup=0),
-                                 dict(expansion_num=1, expansion_den=1), dict(depth=3),
+                                 dict(expansion_num=1, expansion_den=1), dict(depth=4), dict(depth=0),
                                  dict(capacity=1), dict(max_batch=0), dict(max_batch=2000),
                                  dict(score=1), dict(dim=300)])
 def test_invalid_params_are_rejected(L, bad):
@@ -80,8 +80,8 @@ def test_null_arguments_are_rejected_before_any_launch(L):
     st = L.lib.knng_build_exact(ctypes.byref(p), None, 10, None, 0, None, 0, None,
                                 ctypes.byref(out))
     assert st == L.KNNG_EINVAL and out.value is None
-    st = L.lib.knng_search(None, None, 1, None, None, None, None, None, 0, None)
+    st = L.lib.knng_search(None, None, 1, None, None, None, None, None, None, 0, None)
     assert st == L.KNNG_EINVAL
-    st = L.lib.knng_insert_batch(None, None, 1, None, None, None)
+    st = L.lib.knng_insert_batch(None, None, 1, None, None, None, None)
     assert st == L.KNNG_EINVAL
     assert L.lib.knng_size(None) == -1

@@ -163,7 +163,8 @@ def test_small_workload_sequential_inserts_bit_exact(G):
                  (w.expansion_num, w.expansion_den), w.depth)
 
 
-@pytest.mark.parametrize("batches,depth", [([256, 100], 2), ([64, 1, 33], 1), ([17, 200], 2)])
+@pytest.mark.parametrize("batches,depth", [([256, 100], 2), ([64, 1, 33], 1), ([17, 200], 2),
+                                           ([256, 77], 3), ([1, 5, 1], 3)])
 def test_batched_inserts_bit_exact(G, batches, depth):
     X = u8_points(11, 6000 + sum(batches), 64, clusters=8, sigma=10.0)
     say(f"batched inserts {batches} depth={depth}")

@@ -86,7 +86,7 @@ WORKLOADS: dict[str, Workload] = {
         name="u8-d64-n100k-b256", kind="u8", dim=64, k=10, n_initial=100_000,
         n_insert=10_000, batch=256, n_query=10_000, n_clusters=100, sigma=10.0,
         mixture_seed=21, stream_seed=22, query_seed=23,
-        speedup=4, expansion_num=5, expansion_den=1, depth=3),
+        speedup=12, expansion_num=5, expansion_den=1, depth=4),
     # 1,000,000 initial float32 points, d=128, 1,000 clusters (centres N(0,1),
     # sigma U[0.05,0.3]), k=20; 50,000 inserts in batches of 1,024; BF16 scoring.
     "f32-d128-n1m-b1024": Workload(

@@ -129,13 +129,11 @@ size_t take(size_t& cur, size_t bytes) {
 int k_pad_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 
 // Update sizes for DEPTH levels: at most k + k^2 + ... + k^depth processed
-// nodes per new point; the processed set keeps at most half its slots full;
-// a level array holds the largest level that is expanded (k^(depth-1)).
+// nodes per new point; a level array holds the largest level that is
+// expanded (k^(depth-1)).
 struct UpdateSizes {
   int64_t props_per_point = 0;
-  int64_t hash_cap = 0;
   int64_t front_cap = 0;
-  int64_t lds_bytes() const { return (hash_cap + 2 * front_cap) * 4; }
 };
 
 UpdateSizes update_sizes(int k, int depth) {
@@ -148,9 +146,19 @@ UpdateSizes update_sizes(int k, int depth) {
     if (u.props_per_point > (1 << 24)) break;
   }
   if (u.front_cap < k) u.front_cap = k;
-  u.hash_cap = 64;
-  while (u.hash_cap < 2 * u.props_per_point) u.hash_cap <<= 1;
   return u;
+}
+
+// Largest graph the on-chip visited / processed sets can cover.
+knng_status check_lds(int64_t n, const knng_params& p) {
+  const int k_pad = k_pad_of(p.k);
+  if (search_lds_bytes(n, k_pad) > LDS_LIMIT)
+    return fail(KNNG_ECAPACITY, "a graph of %lld nodes exceeds the on-chip visited set of "
+                "this build (%zu bytes of LDS per wavefront)", (long long)n, LDS_LIMIT);
+  if (update_lds_bytes(n, update_sizes(p.k, p.depth).front_cap) > LDS_LIMIT)
+    return fail(KNNG_ECAPACITY, "a graph of %lld nodes with depth %d exceeds the on-chip "
+                "update sets of this build", (long long)n, p.depth);
+  return KNNG_OK;
 }
 
 knng_status check_params(const knng_params* p) {
@@ -173,9 +181,9 @@ knng_status check_params(const knng_params* p) {
   if (p->expansion_den < 1 || p->expansion_num <= p->expansion_den)
     return fail(KNNG_EINVAL, "expansion num/den must be > 1 with den >= 1");
   if (p->depth < 1 || p->depth > 8) return fail(KNNG_EINVAL, "depth must be 1 .. 8");
-  if (update_sizes(p->k, p->depth).lds_bytes() > 65536)
-    return fail(KNNG_EINVAL, "depth %d with k %d needs more than 64 KiB of LDS per update "
-                             "wavefront (k^depth too large)", p->depth, p->k);
+  if (update_lds_bytes(2, update_sizes(p->k, p->depth).front_cap) > LDS_LIMIT)
+    return fail(KNNG_EINVAL, "depth %d with k %d needs level arrays larger than the LDS of "
+                             "one wavefront (k^(depth-1) too large)", p->depth, p->k);
   return KNNG_OK;
 }
 
@@ -203,8 +211,6 @@ WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   W.partial_lists = PARTIAL_LISTS;
   size_t cur = 0;
   const size_t M = (size_t)W.M;
-  W.off_qvec = take(cur, M * S.row_bytes);
-  W.off_qnorm = take(cur, M * 4);
   W.off_res_ids = take(cur, M * S.k_pad * 4);
   W.off_res_d = take(cur, M * S.k_pad * 4);
   W.off_evals = take(cur, M * 4);
@@ -271,8 +277,9 @@ knng_status make_handle(const knng_params* p, void* storage, size_t storage_byte
   return KNNG_OK;
 }
 
-// Search m ingested query rows (at qvec/qnorm) on the current graph.
-knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, int64_t m,
+// Search m queries -- ingested int8 rows (qvec) or raw uint8 points (qraw) --
+// on the current graph.
+knng_status run_search(knng_graph* g, const int8_t* qvec, const uint8_t* qraw, int64_t m,
                        const uint64_t* keys, uint64_t key_base, int32_t* out_ids,
                        int32_t* out_d, int out_stride, int32_t* evals, int32_t* list_reads,
                        int32_t* trace, int64_t trace_stride, int stage, hipStream_t stream) {
@@ -290,7 +297,8 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, 
   a.e_den = g->p.expansion_den;
   a.seed = g->p.seed;
   a.qvec = qvec;
-  a.qnorm = qnorm;
+  a.qraw = qraw;
+  a.dim = S.dim;
   a.m = (int32_t)m;
   a.keys = keys;
   a.key_base = key_base;
@@ -301,10 +309,6 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const int32_t* qnorm, 
   a.out_list_reads = list_reads;
   a.trace = trace;
   a.trace_stride = trace_stride;
-  a.vis_words = (int32_t)((g->n + 31) / 32);
-  if ((size_t)a.vis_words * 4 > 65536)
-    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
-                             "which this build does not provide");
   Timed t(g, stage, stream);
   KNNG_TRY(launch_search_u8(a, stream), "search launch");
   return KNNG_OK;
@@ -450,10 +454,7 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (m == 0) return ok();
-  if (m < 0) return fail(KNNG_EINVAL, "m must be >= 0");
-  if (m > g->W.M)
-    return fail(KNNG_ECAPACITY, "m %lld exceeds max_batch %lld", (long long)m,
-                (long long)g->W.M);
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(KNNG_EINVAL, "m must be in 0 .. 2^31-1");
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
@@ -461,14 +462,8 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   if (trace_dev && trace_stride < budget(g->n, g->S.k, g->p.speedup))
     return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
                 (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
-  if ((g->n + 31) / 32 * 4 > 65536)
-    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
-                             "which this build does not provide");
-  const WorkspaceLayout& W = g->W;
-  int8_t* qv = at<int8_t>(g->ws, W.off_qvec);
-  int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
-  if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
-  s = run_search(g, qv, qn, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
+  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
+  s = run_search(g, nullptr, (const uint8_t*)q_dev, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
                  list_reads_dev, trace_dev, trace_stride, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   return ok();
@@ -480,21 +475,12 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (m == 0) return ok();
-  if (m < 0) return fail(KNNG_EINVAL, "m must be >= 0");
-  if (m > g->W.M)
-    return fail(KNNG_ECAPACITY, "m %lld exceeds max_batch %lld", (long long)m,
-                (long long)g->W.M);
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(KNNG_EINVAL, "m must be in 0 .. 2^31-1");
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
-  if ((g->n + 31) / 32 * 4 > 65536)
-    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
-                             "which this build does not provide");
-  const WorkspaceLayout& W = g->W;
-  int8_t* qv = at<int8_t>(g->ws, W.off_qvec);
-  int32_t* qn = at<int32_t>(g->ws, W.off_qnorm);
-  if ((s = ingest(g, q_dev, m, qv, qn, stream)) != KNNG_OK) return s;
-  s = run_search(g, qv, qn, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
+  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
+  s = run_search(g, nullptr, (const uint8_t*)q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
                  (int32_t*)d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0,
                  KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
@@ -519,9 +505,7 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   if (g->n + b > g->S.cap)
     return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
                 (long long)b, (long long)g->S.cap);
-  if ((g->n + b + 31) / 32 * 4 > 65536)
-    return fail(KNNG_EINVAL, "graphs above 524288 nodes need the hashed visited set, "
-                             "which this build does not provide");
+  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
   const int64_t n = g->n;
@@ -542,7 +526,7 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   //     which only reads nodes < n)
   if ((s = ingest(g, x_dev, b, bvec, bnorm, stream)) != KNNG_OK) return s;
   // (i) iGNNS of every new point on the pre-batch graph, key = its id
-  s = run_search(g, bvec, bnorm, b, nullptr, (uint64_t)n, res_ids, res_d, S.k_pad, evals,
+  s = run_search(g, bvec, nullptr, b, nullptr, (uint64_t)n, res_ids, res_d, S.k_pad, evals,
                  lreads, nullptr, 0, KNNG_STAGE_SEARCH, stream);
   if (s != KNNG_OK) return s;
   // (ii) lists of the new nodes: search result + batch peers
@@ -586,9 +570,8 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   ua.list_reads = lreads;
   ua.sims = sims_dev;
   ua.stats = stats_dev;
-  const UpdateSizes us = update_sizes(S.k, g->p.depth);
-  ua.hash_cap = (int)us.hash_cap;
-  ua.front_cap = (int)us.front_cap;
+  ua.n = (int32_t)n;
+  ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
   {
     Timed t(g, KNNG_STAGE_UPDATE, stream);
     KNNG_TRY(launch_update_u8(ua, stream), "update launch");

@@ -46,6 +46,16 @@ __device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int delta) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// value of a lane chosen by a wave-uniform index (v_readlane: scalar result)
+__device__ __forceinline__ int readlane_i32(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // ballot over the whole wave (64-bit mask)
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -61,7 +71,7 @@ __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a <
 // Inserts `cand` (uniform across the wave) if it beats the current k-th.
 __device__ __forceinline__ void lanes_topk_insert(uint64_t& mine, uint64_t cand, int k) {
   const int lane = lane_id();
-  uint64_t kth = shfl_u64(mine, k - 1);
+  uint64_t kth = readlane_u64(mine, k - 1);
   if (cand >= kth) return;
   int pos = __popcll(ballot(lane < k && mine < cand));
   uint64_t up = shfl_up_u64(mine, 1);
@@ -73,14 +83,115 @@ __device__ __forceinline__ void lanes_topk_insert(uint64_t& mine, uint64_t cand,
 
 // Offer every flagged lane's key to the lane-held top-k list.
 __device__ __forceinline__ void lanes_topk_offer(uint64_t& mine, bool flag, uint64_t key, int k) {
-  uint64_t kth = shfl_u64(mine, k - 1);
+  uint64_t kth = readlane_u64(mine, k - 1);
   uint64_t pass = ballot(flag && key < kth);
   while (pass) {
     int j = __ffsll((long long)pass) - 1;
     pass &= pass - 1;
-    uint64_t cand = shfl_u64(key, j);
+    uint64_t cand = readlane_u64(key, j);
     lanes_topk_insert(mine, cand, k);
   }
+}
+
+// Offer many flagged keys at once (same result as lanes_topk_offer).  When
+// more than two candidates qualify, every qualifying candidate and every
+// list entry computes its rank in the union by counting smaller keys
+// (LDS broadcast reads), and the k smallest are scattered into place.
+// `cbuf`, `rbuf`, `obuf` are 64-entry LDS arrays owned by this wavefront.
+__device__ __forceinline__ void lanes_topk_offer_ranked(uint64_t& mine, bool flag, uint64_t key,
+                                                        int k, uint64_t* cbuf, uint64_t* rbuf,
+                                                        uint64_t* obuf) {
+  const int lane = lane_id();
+  uint64_t kth = readlane_u64(mine, k - 1);
+  bool pass = flag && key < kth;
+  uint64_t P = ballot(pass);
+  int np = __popcll(P);
+  if (np == 0) return;
+  if (np <= 2) {
+    while (P) {
+      int j = __ffsll((long long)P) - 1;
+      P &= P - 1;
+      lanes_topk_insert(mine, readlane_u64(key, j), k);
+    }
+    return;
+  }
+  if (pass) cbuf[rank_below(P)] = key;
+  rbuf[lane] = mine;
+  __syncthreads();
+  // rank of this lane's candidate / list entry in the union
+  int pos = WAVE;
+  if (pass) {
+    int r = 0;
+    for (int t = 0; t < k; ++t) r += rbuf[t] < key;
+    for (int t = 0; t < np; ++t) r += cbuf[t] < key;
+    pos = r;
+  }
+  int rpos = WAVE;
+  if (lane < k && mine != KEY_INF) {
+    int r = lane;
+    for (int t = 0; t < np; ++t) r += cbuf[t] < mine;
+    rpos = r;
+  }
+  obuf[lane] = KEY_INF;
+  __syncthreads();
+  if (pos < k) obuf[pos] = key;
+  if (rpos < k) obuf[rpos] = mine;
+  __syncthreads();
+  mine = lane < k ? obuf[lane] : KEY_INF;
+  __syncthreads();
+}
+
+// The same for a workgroup of exactly one wavefront: LDS accesses of one
+// wavefront complete in order, so wavefront-scope ordering suffices and no
+// workgroup barrier (which would also wait for outstanding global loads)
+// is issued.
+__device__ __forceinline__ void wave_topk_offer_ranked(uint64_t& mine, bool flag, uint64_t key,
+                                                       int k, uint64_t* cbuf, uint64_t* rbuf,
+                                                       uint64_t* obuf) {
+  const int lane = lane_id();
+  uint64_t kth = readlane_u64(mine, k - 1);
+  bool pass = flag && key < kth;
+  uint64_t P = ballot(pass);
+  int np = __popcll(P);
+  if (np == 0) return;
+  if (np <= 2) {
+    while (P) {
+      int j = __ffsll((long long)P) - 1;
+      P &= P - 1;
+      lanes_topk_insert(mine, readlane_u64(key, j), k);
+    }
+    return;
+  }
+  if (pass) cbuf[rank_below(P)] = key;
+  rbuf[lane] = mine;
+  obuf[lane] = KEY_INF;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  int pos = WAVE;
+  if (pass) {
+    int r = 0;
+#pragma unroll 4
+    for (int t = 0; t < k; ++t) r += rbuf[t] < key;
+#pragma unroll 8
+    for (int t = 0; t < np; ++t) r += cbuf[t] < key;
+    pos = r;
+  }
+  int rpos = WAVE;
+  if (lane < k && mine != KEY_INF) {
+    int r = lane;
+#pragma unroll 8
+    for (int t = 0; t < np; ++t) r += cbuf[t] < mine;
+    rpos = r;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (pos < k) obuf[pos] = key;
+  if (rpos < k) obuf[rpos] = mine;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  mine = lane < k ? obuf[lane] : KEY_INF;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ---- register lists: KM keys sorted ascending, compile-time indexed -------

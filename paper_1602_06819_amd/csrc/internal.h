@@ -25,7 +25,6 @@ struct StorageLayout {
 };
 
 // Workspace (calls of up to M points):
-//   qvec/qnorm    ingested query rows (queries and searches)
 //   res_ids/res_d search results [M][k_pad]
 //   evals/upd     per point counters
 //   props         proposals [M * props_per_point] {target, dist, src, next}
@@ -36,7 +35,7 @@ struct WorkspaceLayout {
   int64_t M = 0;
   int64_t props_per_point = 0;
   int64_t partial_lists = 0;   // capacity in lists of k_pad keys
-  size_t off_qvec = 0, off_qnorm = 0, off_res_ids = 0, off_res_d = 0, off_evals = 0,
+  size_t off_res_ids = 0, off_res_d = 0, off_evals = 0,
          off_upd = 0, off_lreads = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
          off_keys = 0, total = 0;
 };
@@ -76,13 +75,16 @@ struct SearchArgs {
   uint32_t m_mod;        // permutation modulus m = 2^ceil(log2 n)
   int32_t e_num, e_den;
   uint64_t seed;
-  const int8_t* qvec; const int32_t* qnorm; int32_t m;
+  const int8_t* qvec;    // ingested query rows [m][row_bytes], or null:
+  const uint8_t* qraw;   // raw uint8 queries [m][dim]
+  int dim;
+  int32_t m;
   const uint64_t* keys; uint64_t key_base;   // key = keys ? keys[i] : key_base + i
   int32_t* out_ids; int32_t* out_d; int out_stride;
   int32_t* out_evals;
   int32_t* out_list_reads;   // neighbour lists read per query (may be null)
   int32_t* trace; int64_t trace_stride;
-  int32_t vis_words;
+  int32_t vis_words, vis_words_pad;   // set by the launcher from n
 };
 
 struct PeerArgs {
@@ -103,7 +105,8 @@ struct UpdateArgs {
   const int32_t* evals; const int32_t* list_reads;
   int32_t* sims;                                  // may be null
   int32_t* stats;                                 // [b][3] or null
-  int hash_cap;          // processed-set slots (power of two)
+  int32_t n;             // snapshot size (processed-set bitset covers [0, n))
+  int32_t set_words, set_words_pad;   // set by the launcher from n
   int front_cap;         // slots of one level array (largest expanded level)
 };
 
@@ -113,6 +116,11 @@ struct MergeArgs {
   const Proposal* props; const int32_t* touched; const int32_t* counters;
   int32_t max_touched;
 };
+
+// ---- LDS needs of the online kernels (bytes per wavefront) -------------------
+size_t search_lds_bytes(int64_t n, int k_pad);
+size_t update_lds_bytes(int64_t n, int64_t front_cap);
+constexpr size_t LDS_LIMIT = 65536;
 
 // ---- launchers (each returns the hipError_t of its launch) ------------------
 hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s);

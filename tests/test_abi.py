@@ -52,7 +52,8 @@ def _p(L, **kw):
 
 
 @pytest.mark.parametrize("bad", [dict(k=0), dict(k=65), dict(dim=0), dict(speedup=0),
-                                 dict(expansion_num=1, expansion_den=1), dict(depth=4), dict(depth=0),
+                                 dict(expansion_num=1, expansion_den=1), dict(depth=9), dict(depth=0),
+                                 dict(k=64, depth=4),
                                  dict(capacity=1), dict(max_batch=0), dict(max_batch=2000),
                                  dict(score=1), dict(dim=300)])
 def test_invalid_params_are_rejected(L, bad):

@@ -164,7 +164,7 @@ def test_small_workload_sequential_inserts_bit_exact(G):
 
 
 @pytest.mark.parametrize("batches,depth", [([256, 100], 2), ([64, 1, 33], 1), ([17, 200], 2),
-                                           ([256, 77], 3), ([1, 5, 1], 3)])
+                                           ([256, 77], 3), ([1, 5, 1], 3), ([256, 130], 4)])
 def test_batched_inserts_bit_exact(G, batches, depth):
     X = u8_points(11, 6000 + sum(batches), 64, clusters=8, sigma=10.0)
     say(f"batched inserts {batches} depth={depth}")

@@ -56,7 +56,28 @@ def parse():
     ap.add_argument("--per-point", type=int, default=256,
                     help="points inserted one at a time for the batch=1 baseline")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
+
+
+def recorded_traffic(grid_threads: int):
+    """HBM bytes per search launch from the committed counter record, or
+    None if there is none or it was taken on a different kernel source."""
+    from paper_1602_06819_amd import profsum
+    path = os.path.join(ROOT, "profiles", "traffic_k_search_u8.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != profsum.search_kernel_hash():
+        return None
+    rows = rec.get("per_grid_kib_per_dispatch", {})
+    fetch = rows.get("FETCH_SIZE", {}).get(str(grid_threads))
+    write = rows.get("WRITE_SIZE", {}).get(str(grid_threads))
+    if fetch is None or write is None or not rec.get("fetch_scale") or not rec.get("write_scale"):
+        return None
+    return 1024.0 * (fetch * rec["fetch_scale"] + write * rec["write_scale"])
 
 
 def cpu_baseline(w, X, params, sample: int):
@@ -184,7 +205,7 @@ def main():
     bytes_per_launch = search_bytes / max(search_launches, 1)
     achieved = bytes_per_launch / (search_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(b * 64),
                 "kernel": "k_search_u8", "avg_launch_ms": search_avg_ms,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
@@ -239,6 +260,16 @@ def main():
         gp.close()
         del gp
         log(f"[bench] per-point insertion (b=1): {per_point:.0f} inserts/s")
+
+    # ---- calibration copy for the HBM byte counters ----------------------------------
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- CPU oracle baseline -----------------------------------------------------
     cpu = None

@@ -1,0 +1,137 @@
+"""Summaries of rocprofv3 CSV output for the committed profile records.
+
+    python -m paper_1602_06819_amd.profsum trace  <dir> <out.md> "<command>"
+    python -m paper_1602_06819_amd.profsum pmc    <fetch_dir> <write_dir> <out.json> \
+        "<fetch command>" "<write command>" <copy_bytes>
+
+`trace` reads a `--kernel-trace --stats -f csv` run and writes per-kernel
+statistics, split by grid size (one kernel serves batches, single points
+and query sets).  `pmc` reads one `--pmc FETCH_SIZE` and one
+`--pmc WRITE_SIZE` run, scales both by what the counters read for the
+calibration copy of `copy_bytes` bytes, and writes the bytes per dispatch
+of the search kernel together with the hash of its source, so that a stale
+record is never reported for a changed kernel.
+"""
+
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SEARCH_SOURCES = ["csrc/online_u8.hip", "csrc/common.h", "csrc/internal.h"]
+
+
+def search_kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in SEARCH_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(directory: str, suffix: str):
+    files = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    for path in files:
+        with open(path, newline="") as f:
+            yield from csv.DictReader(f)
+
+
+def _short(name: str) -> str:
+    name = name.strip('"')
+    return name if len(name) < 90 else name[:87] + "..."
+
+
+def kernel_table(directory: str):
+    stats = defaultdict(list)
+    for r in _rows(directory, "kernel_trace.csv"):
+        name = r.get("Kernel_Name") or r.get("KernelName") or "?"
+        start = int(r.get("Start_Timestamp") or r.get("BeginNs") or 0)
+        end = int(r.get("End_Timestamp") or r.get("EndNs") or 0)
+        grid = r.get("Grid_Size_X") or r.get("Grid_Size") or r.get("grd") or "?"
+        wg = r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or r.get("wgr") or "?"
+        stats[(name, grid, wg)].append((end - start) / 1000.0)
+    return stats
+
+
+def write_trace(directory: str, out: str, command: str) -> None:
+    stats = kernel_table(directory)
+    total = sum(sum(v) for v in stats.values())
+    lines = ["# rocprofv3 kernel trace summary", "", "Command:", "", "```", command, "```", "",
+             "Durations in microseconds, per kernel and grid (threads in x).", "",
+             "| kernel | grid x | wg | calls | avg us | min us | max us | total us | % |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for (name, grid, wg), v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{_short(name)}` | {grid} | {wg} | {len(v)} | {sum(v) / len(v):.1f} | "
+                     f"{min(v):.1f} | {max(v):.1f} | {sum(v):.1f} | {100 * sum(v) / total:.1f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def counter_table(directory: str):
+    vals = defaultdict(list)
+    for r in _rows(directory, "counter_collection.csv"):
+        name = r.get("Kernel_Name", "?")
+        grid = r.get("Grid_Size_X") or r.get("Grid_Size") or "?"
+        cname = r.get("Counter_Name", "?")
+        vals[(name, grid, cname)].append(float(r.get("Counter_Value", "nan")))
+    return vals
+
+
+def write_pmc(fetch_dir: str, write_dir: str, out: str, fetch_cmd: str, write_cmd: str,
+              copy_bytes: int) -> None:
+    fetch = counter_table(fetch_dir)
+    write = counter_table(write_dir)
+
+    def pick(table, kernel_part, counter):
+        # the calibration copy is the largest copy dispatch of the run
+        best = None
+        for (name, grid, cname), v in table.items():
+            if kernel_part in name and cname == counter:
+                if best is None or max(v) > max(best[2]):
+                    best = (name, grid, v)
+        return best
+
+    copy_f = pick(fetch, "copy", "FETCH_SIZE")
+    copy_w = pick(write, "copy", "WRITE_SIZE")
+    # the largest-grid dispatches of the search kernel are the insert batches
+    rows = {}
+    for table, counter in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
+        for (name, grid, cname), v in table.items():
+            if "k_search_u8" in name and cname == counter:
+                rows.setdefault(counter, {})[grid] = sum(v) / len(v)
+    kib = 1024.0
+    scale_f = copy_bytes / (max(copy_f[2]) * kib) if copy_f else None
+    scale_w = copy_bytes / (max(copy_w[2]) * kib) if copy_w else None
+    rec = {
+        "kernel": "k_search_u8",
+        "source_hash": search_kernel_hash(),
+        "fetch_command": fetch_cmd,
+        "write_command": write_cmd,
+        "copy_bytes": copy_bytes,
+        "copy_fetch_kib": max(copy_f[2]) if copy_f else None,
+        "copy_write_kib": max(copy_w[2]) if copy_w else None,
+        "fetch_scale": scale_f,
+        "write_scale": scale_w,
+        "per_grid_kib_per_dispatch": rows,
+    }
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "trace":
+        write_trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif mode == "pmc":
+        write_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
+                  int(sys.argv[7]))
+    else:
+        raise SystemExit(__doc__)

@@ -62,10 +62,11 @@ def parse():
 
 
 def recorded_traffic(grid_threads: int):
-    """HBM bytes per search launch from the committed counter record, or
-    None if there is none or it was taken on a different kernel source."""
+    """HBM bytes per search launch (int8 rows) from the committed counter
+    record, or None if there is none or it was taken on a different kernel
+    source."""
     from paper_1602_06819_amd import profsum
-    path = os.path.join(ROOT, "profiles", "traffic_k_search_u8.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_search_i8.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -142,9 +143,12 @@ def main():
     Qpts = w.queries() if w.n_query else None
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Qpts).to(dev) if Qpts is not None else None
+    is_float = w.kind != "u8"
+    gdt = "f32" if is_float else "u8"
     cfg = GraphConfig(dim=w.dim, k=w.k, capacity=n0 + K * b, max_batch=max(b, w.n_query or 0),
                       speedup=speedup, expansion_num=w.expansion_num,
-                      expansion_den=w.expansion_den, depth=w.depth, seed=w.algo_seed)
+                      expansion_den=w.expansion_den, depth=w.depth, seed=w.algo_seed,
+                      dtype=gdt, score=w.score if is_float else "exact")
 
     # ---- exact initial graph (timed on its own) ----------------------------
     torch.cuda.synchronize()
@@ -165,6 +169,9 @@ def main():
         gw.close()
         del gw
         log(f"[bench] {W} warmup steps done")
+    if is_float:
+        log("[bench] float workload: the CPU oracle leg is not run (its float64 exact "
+            "initial graph of this size does not fit a bounded sample)")
 
     # ---- timed steps ---------------------------------------------------------
     stats = []
@@ -193,20 +200,31 @@ def main():
     log(f"[bench] {K} steps: {value:.0f} inserts/s, {1000 * elapsed / K:.3f} ms/step")
 
     # ---- roofline of the search kernel (dominant) ----------------------------
-    row_bytes = -(-w.dim // 16) * 16
+    # bytes the method reads per evaluated point: its scoring row
+    # (int8: d; bfloat16: 2d; FP8: d codes + a 4-byte scale; float32: 4d)
+    v_bytes = {"u8": w.dim, "bf16": 2 * w.dim, "fp8": w.dim + 4,
+               "exact": 4 * w.dim}["u8" if not is_float else w.score]
+    q_bytes = w.dim if not is_float else 4 * w.dim
+    keep = min(64, 2 * w.k) if is_float and w.score in ("bf16", "fp8") else w.k
     search_ms, search_launches = stage["search"]
     evals_total = st[:, 0].sum()
     lists_total = st[:, 1].sum()
     # algorithmic bytes: every evaluated point's row, every adjacency list
-    # read by the climb (k ids), the query row and the k (id, distance) output
-    search_bytes = (evals_total * row_bytes + lists_total * w.k * 4
-                    + inserts * (row_bytes + w.k * 8))
+    # read by the climb (k ids), the query row and the k (id, distance)
+    # output; float graphs also read the float32 rows of the kept candidates
+    # for the re-rank
+    search_bytes = (evals_total * v_bytes + lists_total * w.k * 4
+                    + inserts * (q_bytes + w.k * 8))
+    if is_float:
+        search_bytes += inserts * keep * 4 * w.dim
     search_avg_ms = search_ms / max(search_launches, 1)
     bytes_per_launch = search_bytes / max(search_launches, 1)
     achieved = bytes_per_launch / (search_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(b * 64),
-                "kernel": "k_search_u8", "avg_launch_ms": search_avg_ms,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None if is_float else recorded_traffic(b * 64),
+                "kernel": f"k_search ({'int8' if not is_float else w.score} rows)",
+                "avg_launch_ms": search_avg_ms,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
     # ---- queries on the final graph -------------------------------------------
@@ -232,7 +250,8 @@ def main():
     if not args.no_recall:
         n_final = n0 + inserts
         ids_online, _ = g.lists()
-        cfg_x = GraphConfig(dim=w.dim, k=w.k, capacity=n_final, max_batch=b, speedup=speedup)
+        cfg_x = GraphConfig(dim=w.dim, k=w.k, capacity=n_final, max_batch=b, speedup=speedup,
+                            dtype=gdt, score="exact")
         gx = KnnGraph.build_exact(cfg_x, Xd[:n_final])
         ids_exact, _ = gx.lists()
         io = ids_online.cpu().numpy()
@@ -273,7 +292,7 @@ def main():
 
     # ---- CPU oracle baseline -----------------------------------------------------
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not is_float:
         import oracle as O
         params = O.Params(k=w.k, speedup=speedup, e_num=w.expansion_num, e_den=w.expansion_den,
                           depth=w.depth, seed=w.algo_seed)
@@ -292,7 +311,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "int8" if not is_float else {"bf16": "bf16", "fp8": "fp8",
+                                               "exact": "f32"}[w.score],
         "data": "synthetic",
         "config": {"workload": w.name, "n_initial": n0, "dim": w.dim, "k": w.k, "batch": b,
                    "inserts": inserts, "speedup": speedup,

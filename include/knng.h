@@ -207,6 +207,23 @@ knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,
 knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count,
                             void* x_dev, hipStream_t stream);
 
+/* Bytes of one scoring row of the search (the layout of knng_get_rows):
+ * uint8 data: dim rounded up to 16 bytes of int8 (coordinate - 128);
+ * float data: 2 * dim rounded up to 16 (KNNG_SCORE_BF16, bfloat16),
+ * dim rounded up to 16 (KNNG_SCORE_FP8, E4M3 codes), or 4 * dim rounded up
+ * to 16 (KNNG_SCORE_EXACT, the float32 rows).  -1 for a NULL handle. */
+int32_t knng_row_bytes(const knng_graph* g);
+
+/* Copy the scoring rows of nodes [first, first + count) out, as stored:
+ * rows_dev [count][knng_row_bytes(g)] bytes (zero padded), and for
+ * KNNG_SCORE_FP8 the row scales scale_dev [count] float (a node's
+ * coordinates are approximated by scale * code).  Either pointer may be
+ * NULL; scale_dev is ignored for other formats.  For checking the
+ * quantizers: bfloat16 by round-to-nearest-even, E4M3 codes
+ * RNE(x / scale) with scale = max |x| / 448 per row. */
+knng_status knng_get_rows(const knng_graph* g, int64_t first, int64_t count, void* rows_dev,
+                          float* scale_dev, hipStream_t stream);
+
 /* Stage timing.  knng_timing_enable(g, 1) clears the accumulated times and
  * from then on records a HIP event pair on the call's stream around every
  * launch of each stage; knng_timing_enable(g, 0) stops recording.

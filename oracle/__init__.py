@@ -23,6 +23,13 @@ silent are listed in each function's docstring):
 * the literal sequential transcription of Algorithms 1 and 2 (adds happen
   immediately), used to pin the batch form    -> :func:`online.insert_sequential_literal`
 * read-only k-nn query on the current graph   -> :func:`online.query`
+* the number formats of the float path's scoring rows (bfloat16, FP8 E4M3
+  with a row scale), from their definitions  -> :mod:`quantize`
+
+Float data: every distance here is float64 computed from the float32
+inputs; the GPU's float path stores float32 distances and may decide near
+ties differently, so its parity is checked by distance error, list
+invariants and agreement rates rather than bit equality.
 
 Parity status: every function is pinned by tests under ``tests/`` against
 brute force, special cases, closed forms or invariants; the approximation
@@ -35,5 +42,6 @@ from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
 from .exact import ExactRows, exact_graph, exact_graph_loops, exact_row  # noqa: F401
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
+from . import quantize  # noqa: F401
 from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401
                      BatchResult, QUERY_KEY_BASE)

@@ -24,7 +24,7 @@ EXPORTED = [
     "knng_storage_bytes", "knng_workspace_bytes", "knng_build_exact", "knng_load",
     "knng_search", "knng_insert_batch", "knng_query", "knng_get_lists", "knng_get_points",
     "knng_size", "knng_query_count", "knng_last_error", "knng_destroy",
-    "knng_timing_enable", "knng_timing_read",
+    "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -93,6 +93,10 @@ def _load() -> ctypes.CDLL:
     lib.knng_timing_enable.restype = ctypes.c_int
     lib.knng_timing_read.argtypes = [vp, P(ctypes.c_double), P(i64)]
     lib.knng_timing_read.restype = ctypes.c_int
+    lib.knng_row_bytes.argtypes = [vp]
+    lib.knng_row_bytes.restype = ctypes.c_int32
+    lib.knng_get_rows.argtypes = [vp, i64, i64, vp, vp, vp]
+    lib.knng_get_rows.restype = ctypes.c_int
     return lib
 
 

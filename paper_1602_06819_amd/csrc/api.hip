@@ -149,16 +149,20 @@ UpdateSizes update_sizes(int k, int depth) {
   return u;
 }
 
-// Largest graph the on-chip visited / processed sets can cover.
-knng_status check_lds(int64_t n, const knng_params& p) {
-  const int k_pad = k_pad_of(p.k);
-  if (search_lds_bytes(n, k_pad) > LDS_LIMIT)
-    return fail(KNNG_ECAPACITY, "a graph of %lld nodes exceeds the on-chip visited set of "
-                "this build (%zu bytes of LDS per wavefront)", (long long)n, LDS_LIMIT);
-  if (update_lds_bytes(n, update_sizes(p.k, p.depth).front_cap) > LDS_LIMIT)
-    return fail(KNNG_ECAPACITY, "a graph of %lld nodes with depth %d exceeds the on-chip "
-                "update sets of this build", (long long)n, p.depth);
-  return KNNG_OK;
+int64_t set_bytes(int64_t n) { return round_up((n + 31) / 32, 4) * 4; }
+
+// Where the visited set of a search and the processed set of an update
+// live: LDS while they fit, else per-block bitsets in the workspace.
+bool search_sets_global(int64_t n) { return (size_t)set_bytes(n) > LDS_SET_LIMIT; }
+bool update_sets_global(int64_t n, int64_t front_cap) {
+  return (size_t)set_bytes(n) + 8 * (size_t)front_cap > LDS_LIMIT;
+}
+
+int row_format(const knng_params& p) {
+  if (p.dtype == KNNG_U8) return ROW_I8;
+  if (p.score == KNNG_SCORE_BF16) return ROW_BF16;
+  if (p.score == KNNG_SCORE_FP8) return ROW_FP8;
+  return ROW_F32;
 }
 
 knng_status check_params(const knng_params* p) {
@@ -167,12 +171,13 @@ knng_status check_params(const knng_params* p) {
   if (p->k < 1 || p->k > 64) return fail(KNNG_EINVAL, "k %d outside 1..64", p->k);
   if (p->dtype != KNNG_U8 && p->dtype != KNNG_F32)
     return fail(KNNG_EINVAL, "unknown dtype %d", p->dtype);
-  if (p->dtype == KNNG_F32)
-    return fail(KNNG_EINVAL, "dtype KNNG_F32 is not available in this build");
+  if (p->score != KNNG_SCORE_EXACT && p->score != KNNG_SCORE_BF16 &&
+      p->score != KNNG_SCORE_FP8)
+    return fail(KNNG_EINVAL, "unknown score %d", p->score);
   if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
     return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
-  if (p->dtype == KNNG_U8 && p->dim > 256)
-    return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
+  if (p->dim > 256)
+    return fail(KNNG_EINVAL, "this build supports dim <= 256 (got %d)", p->dim);
   if (p->capacity < 2 || p->capacity >= ((int64_t)1 << 31))
     return fail(KNNG_EINVAL, "capacity %lld outside 2 .. 2^31-1", (long long)p->capacity);
   if (p->max_batch < 1 || p->max_batch > p->capacity)
@@ -181,7 +186,7 @@ knng_status check_params(const knng_params* p) {
   if (p->expansion_den < 1 || p->expansion_num <= p->expansion_den)
     return fail(KNNG_EINVAL, "expansion num/den must be > 1 with den >= 1");
   if (p->depth < 1 || p->depth > 8) return fail(KNNG_EINVAL, "depth must be 1 .. 8");
-  if (update_lds_bytes(2, update_sizes(p->k, p->depth).front_cap) > LDS_LIMIT)
+  if (update_lds_bytes(0, update_sizes(p->k, p->depth).front_cap, true) > LDS_LIMIT - 4096)
     return fail(KNNG_EINVAL, "depth %d with k %d needs level arrays larger than the LDS of "
                              "one wavefront (k^(depth-1) too large)", p->depth, p->k);
   return KNNG_OK;
@@ -192,10 +197,24 @@ StorageLayout storage_layout(const knng_params& p) {
   S.dim = p.dim;
   S.k = p.k;
   S.k_pad = k_pad_of(p.k);
-  S.row_bytes = (int)round_up(p.dim, 16);
+  S.format = row_format(p);
+  S.is_float = p.dtype == KNNG_F32;
+  S.pad = S.is_float ? (int32_t)0x7f800000 : DIST_PAD_I32;
+  S.mstride = S.is_float ? (int)round_up(p.dim, 4) : 0;
+  switch (S.format) {
+    case ROW_I8: S.row_bytes = (int)round_up(p.dim, 16); break;
+    case ROW_BF16: S.row_bytes = (int)round_up(2 * (int64_t)p.dim, 16); break;
+    case ROW_FP8: S.row_bytes = (int)round_up(p.dim, 16); break;
+    default: S.row_bytes = S.mstride * 4; break;
+  }
   S.cap = p.capacity;
   size_t cur = 0;
-  S.off_vec = take(cur, (size_t)S.cap * S.row_bytes);
+  if (S.is_float) S.off_master = take(cur, (size_t)S.cap * S.mstride * 4);
+  if (S.format == ROW_F32)
+    S.off_vec = S.off_master;
+  else
+    S.off_vec = take(cur, (size_t)S.cap * S.row_bytes);
+  if (S.format == ROW_FP8) S.off_scale = take(cur, (size_t)S.cap * 4);
   S.off_norms = take(cur, (size_t)S.cap * 4);
   S.off_ids = take(cur, (size_t)S.cap * S.k_pad * 4);
   S.off_dist = take(cur, (size_t)S.cap * S.k_pad * 4);
@@ -204,10 +223,16 @@ StorageLayout storage_layout(const knng_params& p) {
   return S;
 }
 
+// Candidates per node of the float exact graph (selected by the float32
+// expansion, then re-ranked).
+int exact_km(int k) { return k <= 20 ? 32 : 64; }
+constexpr int64_t CAND_ROWS = 65536;
+
 WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   WorkspaceLayout W;
   W.M = p.max_batch;
-  W.props_per_point = update_sizes(p.k, p.depth).props_per_point;
+  const UpdateSizes us = update_sizes(p.k, p.depth);
+  W.props_per_point = us.props_per_point;
   W.partial_lists = PARTIAL_LISTS;
   size_t cur = 0;
   const size_t M = (size_t)W.M;
@@ -221,6 +246,15 @@ WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   W.off_counters = take(cur, 256);
   W.off_partial = take(cur, (size_t)W.partial_lists * S.k_pad * 8);
   W.off_keys = take(cur, M * 8);
+  if (search_sets_global(S.cap) || update_sets_global(S.cap, us.front_cap)) {
+    W.set_slots = W.M;
+    W.set_words_pad = set_bytes(S.cap) / 4;
+    W.off_sets = take(cur, (size_t)W.set_slots * W.set_words_pad * 4);
+  }
+  if (S.is_float) {
+    W.cand_rows = S.cap < CAND_ROWS ? S.cap : CAND_ROWS;
+    W.off_cand = take(cur, (size_t)W.cand_rows * exact_km(p.k) * 8);
+  }
   W.total = cur;
   return W;
 }
@@ -277,19 +311,29 @@ knng_status make_handle(const knng_params* p, void* storage, size_t storage_byte
   return KNNG_OK;
 }
 
-// Search m queries -- ingested int8 rows (qvec) or raw uint8 points (qraw) --
-// on the current graph.
-knng_status run_search(knng_graph* g, const int8_t* qvec, const uint8_t* qraw, int64_t m,
+// Search m queries -- ingested int8 rows (qvec, uint8 graphs) or raw points
+// (qraw: uint8 or float32) -- on the current graph.
+knng_status run_search(knng_graph* g, const int8_t* qvec, const void* qraw, int64_t m,
                        const uint64_t* keys, uint64_t key_base, int32_t* out_ids,
                        int32_t* out_d, int out_stride, int32_t* evals, int32_t* list_reads,
                        int32_t* trace, int64_t trace_stride, int stage, hipStream_t stream) {
   const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
   SearchArgs a{};
-  a.vec = at<int8_t>(g->st, S.off_vec);
+  a.format = S.format;
+  a.vec = at<char>(g->st, S.off_vec);
   a.row_bytes = S.row_bytes;
+  a.scale = S.format == ROW_FP8 ? at<float>(g->st, S.off_scale) : nullptr;
+  if (S.is_float) {
+    a.master = at<float>(g->st, S.off_master);
+    a.master_stride = S.mstride;
+    a.master_chunks = S.mstride / 4;
+  }
   a.nbr_ids = at<int32_t>(g->st, S.off_ids);
   a.k = S.k;
   a.k_pad = S.k_pad;
+  // BF16 / FP8 scoring keeps twice as many candidates for the float32 re-rank
+  a.keep = (S.format == ROW_BF16 || S.format == ROW_FP8) ? (2 * S.k < 64 ? 2 * S.k : 64) : S.k;
   a.n = (int32_t)g->n;
   a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
   a.m_mod = modulus_for(g->n);
@@ -305,26 +349,122 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const uint8_t* qraw, i
   a.out_ids = out_ids;
   a.out_d = out_d;
   a.out_stride = out_stride;
+  a.pad_bits = (uint32_t)S.pad;
   a.out_evals = evals;
   a.out_list_reads = list_reads;
   a.trace = trace;
   a.trace_stride = trace_stride;
+  if (search_sets_global(g->n)) {
+    a.gvis = at<uint32_t>(g->ws, W.off_sets);
+    a.gvis_slots = W.set_slots;
+  }
   Timed t(g, stage, stream);
-  KNNG_TRY(launch_search_u8(a, stream), "search launch");
+  KNNG_TRY(launch_search(a, stream), "search launch");
   return KNNG_OK;
 }
 
-knng_status ingest(knng_graph* g, const void* x, int64_t m, int8_t* dst, int32_t* norms,
-                   hipStream_t stream) {
-  IngestArgs a{};
-  a.x = (const uint8_t*)x;
-  a.dst = dst;
-  a.norms = norms;
-  a.m = m;
-  a.dim = g->S.dim;
-  a.row_bytes = g->S.row_bytes;
+// Points -> stored rows (scoring rows, norms, float32 rows) at node ids
+// first .. first + m - 1.
+knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipStream_t stream) {
+  const StorageLayout& S = g->S;
   Timed t(g, KNNG_STAGE_INGEST, stream);
-  KNNG_TRY(launch_ingest_u8(a, stream), "ingest launch");
+  if (!S.is_float) {
+    IngestArgs a{};
+    a.x = (const uint8_t*)x;
+    a.dst = at<int8_t>(g->st, S.off_vec) + first * S.row_bytes;
+    a.norms = at<int32_t>(g->st, S.off_norms) + first;
+    a.m = m;
+    a.dim = S.dim;
+    a.row_bytes = S.row_bytes;
+    KNNG_TRY(launch_ingest_u8(a, stream), "ingest launch");
+  } else {
+    IngestF32Args a{};
+    a.x = (const float*)x;
+    a.master = at<float>(g->st, S.off_master) + first * S.mstride;
+    a.norms = at<float>(g->st, S.off_norms) + first;
+    a.score = S.format == ROW_F32 ? nullptr : at<char>(g->st, S.off_vec) + first * S.row_bytes;
+    a.scale = S.format == ROW_FP8 ? at<float>(g->st, S.off_scale) + first : nullptr;
+    a.m = m;
+    a.dim = S.dim;
+    a.stride = S.mstride;
+    a.row_bytes = S.row_bytes;
+    a.format = S.format;
+    KNNG_TRY(launch_ingest_f32(a, stream), "ingest launch");
+  }
+  return KNNG_OK;
+}
+
+// Exact lists of the n stored points (uint8: int8 MFMA tiles, split over
+// the database for small n; float32: float32 MFMA candidates per chunk of
+// nodes, then the float32 re-rank).
+knng_status exact_lists(knng_graph* g, int64_t n, hipStream_t stream) {
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  int32_t* ids = at<int32_t>(g->st, S.off_ids);
+  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  Timed t(g, KNNG_STAGE_EXACT, stream);
+  ExactArgs a{};
+  a.qvec = S.is_float ? (const void*)at<float>(g->st, S.off_master)
+                      : (const void*)at<int8_t>(g->st, S.off_vec);
+  a.qnorm = at<uint32_t>(g->st, S.off_norms);
+  a.nq = (int32_t)n;
+  a.q_id_base = 0;
+  a.dvec = a.qvec;
+  a.dnorm = a.qnorm;
+  a.nd = (int32_t)n;
+  a.d_id_base = 0;
+  a.row_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
+  a.k = S.k;
+  a.exclude_self = 1;
+  if (S.is_float) {
+    const int km = exact_km(S.k);
+    uint64_t* cand = at<uint64_t>(g->ws, W.off_cand);
+    for (int64_t q0 = 0; q0 < n; q0 += W.cand_rows) {
+      const int64_t nq = n - q0 < W.cand_rows ? n - q0 : W.cand_rows;
+      ExactArgs c = a;
+      c.qvec = at<float>(g->st, S.off_master) + q0 * S.mstride;
+      c.qnorm = at<uint32_t>(g->st, S.off_norms) + q0;
+      c.nq = (int32_t)nq;
+      c.q_id_base = (int32_t)q0;
+      c.split_len = (int32_t)n;
+      c.nsplit = 1;
+      c.cand = cand;
+      KNNG_TRY(launch_exact_f32(c, km, stream), "exact launch");
+      RerankArgs r{};
+      r.rows = at<float>(g->st, S.off_master);
+      r.stride = S.mstride;
+      r.dim = S.dim;
+      r.q_id_base = (int32_t)q0;
+      r.nq = (int32_t)nq;
+      r.cand = cand;
+      r.km = km;
+      r.k = S.k;
+      r.out_ids = ids + q0 * S.k_pad;
+      r.out_d = dist + q0 * S.k_pad;
+      r.out_stride = S.k_pad;
+      KNNG_TRY(launch_rerank_f32(r, stream), "re-rank launch");
+    }
+    return KNNG_OK;
+  }
+  a.out_ids = ids;
+  a.out_d = dist;
+  a.out_stride = S.k_pad;
+  a.partial = at<uint64_t>(g->ws, W.off_partial);
+  const int qt = S.k_pad == 64 ? 1 : 2;
+  const int64_t bx = (n + 64 * qt - 1) / (64 * qt);
+  int64_t nsplit = (1024 + bx - 1) / bx;
+  if (nsplit > 64) nsplit = 64;
+  while (nsplit > 1 && nsplit * n > W.partial_lists) --nsplit;
+  if (nsplit < 1) nsplit = 1;
+  int64_t split_len = round_up((n + nsplit - 1) / nsplit, 64);
+  nsplit = (n + split_len - 1) / split_len;
+  a.split_len = (int32_t)split_len;
+  a.nsplit = (int32_t)nsplit;
+  KNNG_TRY(launch_exact_u8(a, stream), "exact launch");
+  if (nsplit > 1)
+    KNNG_TRY(launch_split_merge(a.partial, (int32_t)n, (int32_t)nsplit, S.k, ids, dist, S.k_pad,
+                                stream),
+             "split merge launch");
   return KNNG_OK;
 }
 
@@ -357,53 +497,15 @@ knng_status knng_build_exact(const knng_params* p, const void* x_dev, int64_t n,
   s = make_handle(p, storage_dev, storage_bytes, workspace_dev, workspace_bytes, &g);
   if (s != KNNG_OK) return s;
   const StorageLayout& S = g->S;
-  const WorkspaceLayout& W = g->W;
-  int8_t* vec = at<int8_t>(g->st, S.off_vec);
-  int32_t* norms = at<int32_t>(g->st, S.off_norms);
-  int32_t* ids = at<int32_t>(g->st, S.off_ids);
-  int32_t* dist = at<int32_t>(g->st, S.off_dist);
   auto cleanup = [&](knng_status st) {
     delete g;
     return st;
   };
-  if ((s = ingest(g, x_dev, n, vec, norms, stream)) != KNNG_OK) return cleanup(s);
+  if ((s = ingest(g, x_dev, n, 0, stream)) != KNNG_OK) return cleanup(s);
   if ((s = dev(launch_fill_i32(at<int32_t>(g->st, S.off_head), S.cap, -1, stream), "fill")) !=
       KNNG_OK)
     return cleanup(s);
-
-  ExactArgs a{};
-  a.qvec = vec;
-  a.qnorm = norms;
-  a.nq = (int32_t)n;
-  a.q_id_base = 0;
-  a.dvec = vec;
-  a.dnorm = norms;
-  a.nd = (int32_t)n;
-  a.d_id_base = 0;
-  a.row_bytes = S.row_bytes;
-  a.k = S.k;
-  a.exclude_self = 1;
-  a.out_ids = ids;
-  a.out_d = dist;
-  a.out_stride = S.k_pad;
-  a.partial = at<uint64_t>(g->ws, W.off_partial);
-  const int qt = S.k_pad == 64 ? 1 : 2;
-  const int64_t bx = (n + 64 * qt - 1) / (64 * qt);
-  int64_t nsplit = (1024 + bx - 1) / bx;
-  if (nsplit > 64) nsplit = 64;
-  while (nsplit > 1 && nsplit * n > W.partial_lists) --nsplit;
-  if (nsplit < 1) nsplit = 1;
-  int64_t split_len = round_up((n + nsplit - 1) / nsplit, 64);
-  nsplit = (n + split_len - 1) / split_len;
-  a.split_len = (int32_t)split_len;
-  a.nsplit = (int32_t)nsplit;
-  if ((s = dev(launch_exact_u8(a, stream), "exact launch")) != KNNG_OK) return cleanup(s);
-  if (nsplit > 1) {
-    if ((s = dev(launch_split_merge(a.partial, (int32_t)n, (int32_t)nsplit, S.k, ids, dist,
-                                    S.k_pad, stream),
-                 "split merge launch")) != KNNG_OK)
-      return cleanup(s);
-  }
+  if ((s = exact_lists(g, n, stream)) != KNNG_OK) return cleanup(s);
   g->n = n;
   *out = g;
   return ok();
@@ -431,15 +533,13 @@ knng_status knng_load(const knng_params* p, const void* x_dev, int64_t n, const 
     delete g;
     return st;
   };
-  if ((s = ingest(g, x_dev, n, at<int8_t>(g->st, S.off_vec), at<int32_t>(g->st, S.off_norms),
-                  stream)) != KNNG_OK)
-    return cleanup(s);
+  if ((s = ingest(g, x_dev, n, 0, stream)) != KNNG_OK) return cleanup(s);
   if ((s = dev(launch_fill_i32(at<int32_t>(g->st, S.off_head), S.cap, -1, stream), "fill")) !=
       KNNG_OK)
     return cleanup(s);
   if ((s = dev(launch_copy_lists(ids_dev, (const int32_t*)d_dev, S.k,
                                  at<int32_t>(g->st, S.off_ids), at<int32_t>(g->st, S.off_dist),
-                                 S.k_pad, n, S.k, n, stream),
+                                 S.k_pad, n, S.k, n, S.pad, stream),
                "copy lists")) != KNNG_OK)
     return cleanup(s);
   g->n = n;
@@ -462,8 +562,7 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   if (trace_dev && trace_stride < budget(g->n, g->S.k, g->p.speedup))
     return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
                 (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
-  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
-  s = run_search(g, nullptr, (const uint8_t*)q_dev, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
+  s = run_search(g, nullptr, q_dev, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
                  list_reads_dev, trace_dev, trace_stride, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   return ok();
@@ -479,8 +578,7 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
-  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
-  s = run_search(g, nullptr, (const uint8_t*)q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
+  s = run_search(g, nullptr, q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
                  (int32_t*)d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0,
                  KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
@@ -505,12 +603,9 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   if (g->n + b > g->S.cap)
     return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
                 (long long)b, (long long)g->S.cap);
-  if ((s = check_lds(g->n, g->p)) != KNNG_OK) return s;
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
   const int64_t n = g->n;
-  int8_t* vec = at<int8_t>(g->st, S.off_vec);
-  int32_t* norms = at<int32_t>(g->st, S.off_norms);
   int32_t* ids = at<int32_t>(g->st, S.off_ids);
   int32_t* dist = at<int32_t>(g->st, S.off_dist);
   int32_t* head = at<int32_t>(g->st, S.off_head);
@@ -519,45 +614,52 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   int32_t* evals = at<int32_t>(g->ws, W.off_evals);
   int32_t* lreads = at<int32_t>(g->ws, W.off_lreads);
   int32_t* counters = at<int32_t>(g->ws, W.off_counters);
-  int8_t* bvec = vec + n * S.row_bytes;
-  int32_t* bnorm = norms + n;
+  // rows of the distance evaluations after the search: int8 rows, or the
+  // float32 rows of float graphs
+  const int eval_format = S.is_float ? ROW_F32 : ROW_I8;
+  const char* eval_rows = S.is_float ? at<char>(g->st, S.off_master) : at<char>(g->st, S.off_vec);
+  const int eval_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
 
   // (0) the new points, stored at their ids (not visible to the search,
   //     which only reads nodes < n)
-  if ((s = ingest(g, x_dev, b, bvec, bnorm, stream)) != KNNG_OK) return s;
+  if ((s = ingest(g, x_dev, b, n, stream)) != KNNG_OK) return s;
   // (i) iGNNS of every new point on the pre-batch graph, key = its id
-  s = run_search(g, bvec, nullptr, b, nullptr, (uint64_t)n, res_ids, res_d, S.k_pad, evals,
-                 lreads, nullptr, 0, KNNG_STAGE_SEARCH, stream);
+  const int8_t* bvec = S.is_float ? nullptr : at<int8_t>(g->st, S.off_vec) + n * S.row_bytes;
+  s = run_search(g, bvec, S.is_float ? x_dev : nullptr, b, nullptr, (uint64_t)n, res_ids, res_d,
+                 S.k_pad, evals, lreads, nullptr, 0, KNNG_STAGE_SEARCH, stream);
   if (s != KNNG_OK) return s;
   // (ii) lists of the new nodes: search result + batch peers
   PeerArgs pa{};
-  pa.bvec = bvec;
-  pa.bnorm = bnorm;
+  pa.format = eval_format;
+  pa.bvec = eval_rows + n * eval_bytes;
+  pa.row_bytes = eval_bytes;
+  pa.dim = S.dim;
   pa.b = (int32_t)b;
   pa.id_base = (int32_t)n;
-  pa.row_bytes = S.row_bytes;
   pa.k = S.k;
   pa.k_pad = S.k_pad;
   pa.res_ids = res_ids;
   pa.res_d = res_d;
   pa.list_ids = ids + n * S.k_pad;
   pa.list_d = dist + n * S.k_pad;
+  pa.pad = S.pad;
   {
     Timed t(g, KNNG_STAGE_PEERS, stream);
-    KNNG_TRY(launch_peers_u8(pa, stream), "peers launch");
+    KNNG_TRY(launch_peers(pa, stream), "peers launch");
   }
   // (iii) update proposals on the pre-batch lists
   KNNG_TRY(launch_fill_i32(counters, 2, 0, stream), "fill");
   UpdateArgs ua{};
-  ua.vec = vec;
-  ua.row_bytes = S.row_bytes;
+  ua.format = eval_format;
+  ua.vec = eval_rows;
+  ua.row_bytes = eval_bytes;
+  ua.dim = S.dim;
   ua.nbr_ids = ids;
   ua.nbr_d = dist;
   ua.k = S.k;
   ua.k_pad = S.k_pad;
   ua.head = head;
-  ua.bvec = bvec;
-  ua.bnorm = bnorm;
+  ua.bvec = eval_rows + n * eval_bytes;
   ua.b = (int32_t)b;
   ua.id_base = (int32_t)n;
   ua.res_ids = res_ids;
@@ -572,9 +674,13 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   ua.stats = stats_dev;
   ua.n = (int32_t)n;
   ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
+  if (update_sets_global(n, ua.front_cap)) {
+    ua.gset = at<uint32_t>(g->ws, W.off_sets);
+    ua.gset_slots = W.set_slots;
+  }
   {
     Timed t(g, KNNG_STAGE_UPDATE, stream);
-    KNNG_TRY(launch_update_u8(ua, stream), "update launch");
+    KNNG_TRY(launch_update(ua, stream), "update launch");
   }
   // (iv) merge proposals into the pre-batch lists
   MergeArgs ma{};
@@ -587,6 +693,7 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   ma.touched = ua.touched;
   ma.counters = counters;
   ma.max_touched = (int32_t)(b * W.props_per_point);
+  ma.pad = S.pad;
   {
     Timed t(g, KNNG_STAGE_MERGE, stream);
     KNNG_TRY(launch_merge(ma, stream), "merge launch");
@@ -607,7 +714,7 @@ knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count, in
   const StorageLayout& S = g->S;
   KNNG_TRY(launch_copy_lists(at<int32_t>(g->st, S.off_ids) + first * S.k_pad,
                              at<int32_t>(g->st, S.off_dist) + first * S.k_pad, S.k_pad, ids_dev,
-                             (int32_t*)d_dev, S.k, count, S.k, g->n, stream),
+                             (int32_t*)d_dev, S.k, count, S.k, g->n, S.pad, stream),
            "copy lists");
   return ok();
 }
@@ -620,9 +727,34 @@ knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count, v
     return fail(KNNG_EINVAL, "rows outside the graph");
   if (count == 0) return ok();
   const StorageLayout& S = g->S;
-  KNNG_TRY(launch_export_u8(at<int8_t>(g->st, S.off_vec) + first * S.row_bytes, S.row_bytes,
-                            S.dim, count, (uint8_t*)x_dev, stream),
-           "export points");
+  if (S.is_float)
+    KNNG_TRY(launch_export_f32(at<float>(g->st, S.off_master) + first * S.mstride, S.mstride,
+                               S.dim, count, (float*)x_dev, stream),
+             "export points");
+  else
+    KNNG_TRY(launch_export_u8(at<int8_t>(g->st, S.off_vec) + first * S.row_bytes, S.row_bytes,
+                              S.dim, count, (uint8_t*)x_dev, stream),
+             "export points");
+  return ok();
+}
+
+int32_t knng_row_bytes(const knng_graph* g) { return g ? g->S.row_bytes : -1; }
+
+knng_status knng_get_rows(const knng_graph* g, int64_t first, int64_t count, void* rows_dev,
+                          float* scale_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (first < 0 || count < 0 || first + count > g->n)
+    return fail(KNNG_EINVAL, "rows outside the graph");
+  if (count == 0) return ok();
+  const StorageLayout& S = g->S;
+  if (rows_dev)
+    KNNG_TRY(hipMemcpyAsync(rows_dev, at<char>(g->st, S.off_vec) + first * S.row_bytes,
+                            (size_t)count * S.row_bytes, hipMemcpyDeviceToDevice, stream),
+             "copy rows");
+  if (scale_dev && S.format == ROW_FP8)
+    KNNG_TRY(hipMemcpyAsync(scale_dev, at<float>(g->st, S.off_scale) + first,
+                            (size_t)count * 4, hipMemcpyDeviceToDevice, stream),
+             "copy scales");
   return ok();
 }
 

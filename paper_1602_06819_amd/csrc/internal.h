@@ -12,16 +12,28 @@ namespace knng {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Scoring-row formats of the search.
+enum RowFormat { ROW_I8 = 0, ROW_BF16 = 1, ROW_FP8 = 2, ROW_F32 = 3 };
+
 // Storage (one graph at capacity N):
-//   vec    [N][row_bytes]  int8 rows  (uint8 coordinate - 128, zero padded)
-//   norms  [N]             int32      (sum of squares of the int8 row)
+//   vec    [N][row_bytes]  scoring rows: int8 (uint8 coordinate - 128),
+//                          bfloat16 or FP8 E4M3 codes; zero padded.  For
+//                          float32 scoring this is the master array itself.
+//   scale  [N]             float32 row scale (FP8 only)
+//   master [N][mstride]    float32 rows (float graphs; mstride = dim rounded
+//                          up to 4)
+//   norms  [N]             squared norm: int32 (uint8 graphs) or float32
 //   ids    [N][k_pad]      int32      list ids, sorted by (distance, id)
-//   dist   [N][k_pad]      int32      list distances (padding INT32_MAX / -1)
+//   dist   [N][k_pad]      32-bit distance patterns (int32, or float32 bits);
+//                          padding: id -1 and the largest pattern
 //   head   [N]             int32      first pending proposal per node (-1)
 struct StorageLayout {
-  int dim = 0, k = 0, k_pad = 0, row_bytes = 0;
+  int dim = 0, k = 0, k_pad = 0, row_bytes = 0, format = ROW_I8, mstride = 0;
+  bool is_float = false;
+  int32_t pad = 0;     // distance padding pattern
   int64_t cap = 0;
-  size_t off_vec = 0, off_norms = 0, off_ids = 0, off_dist = 0, off_head = 0, total = 0;
+  size_t off_vec = 0, off_scale = 0, off_master = 0, off_norms = 0, off_ids = 0, off_dist = 0,
+         off_head = 0, total = 0;
 };
 
 // Workspace (calls of up to M points):
@@ -31,13 +43,19 @@ struct StorageLayout {
 //   touched       targets with at least one proposal
 //   counters      [0] proposals, [1] touched
 //   partial       brute-force split partial lists (keys)
+//   keys          restart keys of a call
+//   sets          visited / processed bitsets in global memory, one per
+//                 block, for graphs whose bitset does not fit in LDS
+//   cand          float exact graph: candidate keys of a chunk of nodes
 struct WorkspaceLayout {
   int64_t M = 0;
   int64_t props_per_point = 0;
   int64_t partial_lists = 0;   // capacity in lists of k_pad keys
+  int64_t set_slots = 0, set_words_pad = 0;
+  int64_t cand_rows = 0;
   size_t off_res_ids = 0, off_res_d = 0, off_evals = 0,
          off_upd = 0, off_lreads = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
-         off_keys = 0, total = 0;
+         off_keys = 0, off_sets = 0, off_cand = 0, total = 0;
 };
 
 struct Proposal {
@@ -56,49 +74,78 @@ struct IngestArgs {
   int dim, row_bytes;
 };
 
+struct IngestF32Args {
+  const float* x;      // [m][dim]
+  float* master;       // [m][stride]
+  float* norms;        // [m]
+  char* score;         // [m][row_bytes] (BF16 / FP8 formats)
+  float* scale;        // [m] (FP8)
+  int64_t m;
+  int dim, stride, row_bytes, format;
+};
+
 struct ExactArgs {
-  const int8_t* qvec; const int32_t* qnorm; int32_t nq; int32_t q_id_base;
-  const int8_t* dvec; const int32_t* dnorm; int32_t nd; int32_t d_id_base;
+  const void* qvec; const uint32_t* qnorm; int32_t nq; int32_t q_id_base;
+  const void* dvec; const uint32_t* dnorm; int32_t nd; int32_t d_id_base;
   int row_bytes, k;
   int32_t split_len;     // database rows per split (multiple of the tile)
   int32_t nsplit;
   int exclude_self;      // skip database id == query id
-  int32_t* out_ids; int32_t* out_d; int out_stride;   // when nsplit == 1
+  int32_t* out_ids; int32_t* out_d; int out_stride;   // when nsplit == 1 and no cand
   uint64_t* partial;     // [nsplit][nq][k] keys when nsplit > 1
+  uint64_t* cand;        // float32: [nq][km] candidate keys
+};
+
+struct RerankArgs {
+  const float* rows; int stride; int dim;   // float32 rows of the graph
+  int32_t q_id_base; int32_t nq;            // nodes q_id_base .. + nq - 1
+  const uint64_t* cand; int km;             // [nq][km] candidate keys
+  int k;
+  int32_t* out_ids; int32_t* out_d; int out_stride;
 };
 
 struct SearchArgs {
-  const int8_t* vec; int row_bytes;
+  int format;                              // RowFormat of vec
+  const void* vec; int row_bytes;          // scoring rows
+  const float* scale;                      // FP8 row scales
+  const float* master; int master_stride; int master_chunks;   // float graphs (re-rank)
   const int32_t* nbr_ids; int k, k_pad;
+  int keep;              // result entries kept by the search (k, more before a re-rank)
   int32_t n;             // snapshot size
   int32_t B;             // budget
   uint32_t m_mod;        // permutation modulus m = 2^ceil(log2 n)
   int32_t e_num, e_den;
   uint64_t seed;
-  const int8_t* qvec;    // ingested query rows [m][row_bytes], or null:
-  const uint8_t* qraw;   // raw uint8 queries [m][dim]
+  const int8_t* qvec;    // uint8 graphs: ingested query rows [m][row_bytes], or null:
+  const void* qraw;      // raw queries [m][dim] (uint8 or float32)
   int dim;
   int32_t m;
   const uint64_t* keys; uint64_t key_base;   // key = keys ? keys[i] : key_base + i
   int32_t* out_ids; int32_t* out_d; int out_stride;
+  uint32_t pad_bits;     // distance padding of absent entries
   int32_t* out_evals;
   int32_t* out_list_reads;   // neighbour lists read per query (may be null)
   int32_t* trace; int64_t trace_stride;
-  int32_t vis_words, vis_words_pad;   // set by the launcher from n
+  uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
+  int32_t vis_words, vis_words_pad;    // set by the launcher from n
 };
 
 struct PeerArgs {
-  const int8_t* bvec; const int32_t* bnorm; int32_t b; int32_t id_base;   // batch rows, ids id_base + i
-  int row_bytes, k, k_pad;
+  int format;                                     // ROW_I8 or ROW_F32 (float rows)
+  const void* bvec; int row_bytes; int dim;       // batch rows, ids id_base + i
+  int32_t b; int32_t id_base;
+  int k, k_pad;
   const int32_t* res_ids; const int32_t* res_d;   // search results [b][k_pad]
   int32_t* list_ids; int32_t* list_d;             // lists of the new nodes [b][k_pad]
+  int32_t pad;
 };
 
 struct UpdateArgs {
-  const int8_t* vec; int row_bytes;
+  int format;                                     // ROW_I8 or ROW_F32 (float rows)
+  const void* vec; int row_bytes; int dim;        // rows of the distance evaluations
   int32_t* nbr_ids; int32_t* nbr_d; int k, k_pad;
   int32_t* head;
-  const int8_t* bvec; const int32_t* bnorm; int32_t b; int32_t id_base;
+  const void* bvec; int32_t b; int32_t id_base;
   const int32_t* res_ids; const int32_t* res_d;
   int depth;
   Proposal* props; int32_t* touched; int32_t* counters;
@@ -106,6 +153,7 @@ struct UpdateArgs {
   int32_t* sims;                                  // may be null
   int32_t* stats;                                 // [b][3] or null
   int32_t n;             // snapshot size (processed-set bitset covers [0, n))
+  uint32_t* gset; int64_t gset_slots;             // global processed sets (null: LDS)
   int32_t set_words, set_words_pad;   // set by the launcher from n
   int front_cap;         // slots of one level array (largest expanded level)
 };
@@ -115,27 +163,38 @@ struct MergeArgs {
   int32_t* head;
   const Proposal* props; const int32_t* touched; const int32_t* counters;
   int32_t max_touched;
+  int32_t pad;
 };
 
 // ---- LDS needs of the online kernels (bytes per wavefront) -------------------
-size_t search_lds_bytes(int64_t n, int k_pad);
-size_t update_lds_bytes(int64_t n, int64_t front_cap);
+size_t search_lds_bytes(int64_t n, int k_pad, bool global_visited);
+size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set);
 constexpr size_t LDS_LIMIT = 65536;
+// Bitsets up to this size stay in LDS; larger graphs use global bitsets.
+constexpr size_t LDS_SET_LIMIT = 40960;
 
 // ---- launchers (each returns the hipError_t of its launch) ------------------
 hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s);
+hipError_t launch_ingest_f32(const IngestF32Args& a, hipStream_t s);
 hipError_t launch_exact_u8(const ExactArgs& a, hipStream_t s);
+hipError_t launch_exact_f32(const ExactArgs& a, int km, hipStream_t s);
+hipError_t launch_rerank_f32(const RerankArgs& a, hipStream_t s);
 hipError_t launch_split_merge(const uint64_t* partial, int32_t nq, int32_t nsplit, int k,
                               int32_t* out_ids, int32_t* out_d, int out_stride, hipStream_t s);
-hipError_t launch_search_u8(const SearchArgs& a, hipStream_t s);
-hipError_t launch_peers_u8(const PeerArgs& a, hipStream_t s);
-hipError_t launch_update_u8(const UpdateArgs& a, hipStream_t s);
+hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
+hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
+hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
+hipError_t launch_peers(const PeerArgs& a, hipStream_t s);
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit, hipStream_t s);
+                             int k, int64_t id_limit, int32_t pad, hipStream_t s);
 hipError_t launch_export_u8(const int8_t* vec, int row_bytes, int dim, int64_t rows,
                             uint8_t* out, hipStream_t s);
+hipError_t launch_export_f32(const float* rows, int stride, int dim, int64_t count, float* out,
+                             hipStream_t s);
 
 }  // namespace knng

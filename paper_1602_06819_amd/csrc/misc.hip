@@ -7,7 +7,15 @@
 // int8 MFMA instructions directly.  Rows are zero padded to row_bytes (a
 // multiple of 16); padding contributes nothing to any distance.  The row's
 // squared norm (an int32: at most 4096 * 128^2) is stored beside it.
+//
+// Ingest of float32 points: the float32 row itself (zero padded to a
+// multiple of 4 coordinates: the rows of the stored float distances), its
+// squared norm (for the exact graph's expansion), and the scoring row of
+// the search: bfloat16 by round-to-nearest-even, or FP8 E4M3 codes
+// RNE(x / s) with one scale s = max |x| / 448 per row (s = 0 for a zero
+// row, whose codes are then all zero).
 #include "common.h"
+#include "device.h"
 #include "internal.h"
 
 namespace knng {
@@ -43,6 +51,46 @@ hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One wave per row; lane j takes coordinates j, j + 64, ...
+__global__ __launch_bounds__(256) void k_ingest_f32(IngestF32Args a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.m) return;
+  const float* src = a.x + row * a.dim;
+  float* mrow = a.master + row * a.stride;
+  float nrm = 0.f, mx = 0.f;
+  for (int j = lane; j < a.stride; j += WAVE) {
+    const float v = j < a.dim ? src[j] : 0.f;
+    mrow[j] = v;
+    nrm = __builtin_fmaf(v, v, nrm);
+    mx = fmaxf(mx, fabsf(v));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    nrm += __shfl_xor(nrm, off, WAVE);
+    mx = fmaxf(mx, __shfl_xor(mx, off, WAVE));
+  }
+  if (lane == 0) a.norms[row] = nrm;
+  if (a.format == ROW_BF16) {
+    uint16_t* brow = reinterpret_cast<uint16_t*>(a.score + row * a.row_bytes);
+    for (int j = lane; j < a.row_bytes / 2; j += WAVE)
+      brow[j] = (uint16_t)(j < a.dim ? f32_to_bf16(src[j]) : 0u);
+  } else if (a.format == ROW_FP8) {
+    const float scale = mx / 448.f;
+    uint8_t* frow = reinterpret_cast<uint8_t*>(a.score + row * a.row_bytes);
+    for (int j = lane; j < a.row_bytes; j += WAVE)
+      frow[j] = (uint8_t)((j < a.dim && scale > 0.f) ? f32_to_e4m3(src[j] / scale) : 0u);
+    if (lane == 0) a.scale[row] = scale;
+  }
+}
+
+hipError_t launch_ingest_f32(const IngestF32Args& a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.m + 3) / 4));
+  hipLaunchKernelGGL(k_ingest_f32, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -63,7 +111,7 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) 
 // never make a kernel read outside the graph.
 __global__ void k_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit) {
+                             int k, int64_t id_limit, int32_t pad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = rows * dst_stride;
   if (i >= total) return;
@@ -73,20 +121,21 @@ __global__ void k_copy_lists(const int32_t* src_ids, const int32_t* src_d, int s
     int32_t id = src_ids ? src_ids[r * src_stride + j] : -1;
     bool ok = id >= 0 && (int64_t)id < id_limit;
     if (dst_ids) dst_ids[i] = ok ? id : -1;
-    if (dst_d) dst_d[i] = (ok && src_d) ? src_d[r * src_stride + j] : DIST_PAD_I32;
+    if (dst_d) dst_d[i] = (ok && src_d) ? src_d[r * src_stride + j] : pad;
   } else {
     if (dst_ids) dst_ids[i] = -1;
-    if (dst_d) dst_d[i] = DIST_PAD_I32;
+    if (dst_d) dst_d[i] = pad;
   }
 }
 
 hipError_t launch_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit, hipStream_t s) {
+                             int k, int64_t id_limit, int32_t pad, hipStream_t s) {
   int64_t total = rows * dst_stride;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_lists, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     src_ids, src_d, src_stride, dst_ids, dst_d, dst_stride, rows, k, id_limit);
+                     src_ids, src_d, src_stride, dst_ids, dst_d, dst_stride, rows, k, id_limit,
+                     pad);
   return hipGetLastError();
 }
 
@@ -106,6 +155,24 @@ hipError_t launch_export_u8(const int8_t* vec, int row_bytes, int dim, int64_t r
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_export_u8, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, vec,
                      row_bytes, dim, rows, out);
+  return hipGetLastError();
+}
+
+// float32 rows (stride floats) back to points of dim coordinates.
+__global__ void k_export_f32(const float* rows, int stride, int dim, int64_t count, float* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count * dim) return;
+  int64_t r = i / dim;
+  int j = (int)(i - r * dim);
+  out[i] = rows[r * stride + j];
+}
+
+hipError_t launch_export_f32(const float* rows, int stride, int dim, int64_t count, float* out,
+                             hipStream_t s) {
+  int64_t total = count * dim;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_f32, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows,
+                     stride, dim, count, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,481 @@
+// iGNNS (Section 3 of the paper), one wavefront per query, for every row
+// format of the library:
+//
+//   ScoreI8    int8 rows (uint8 coordinate - 128): exact int32 squared L2
+//   ScoreBF16  bfloat16 rows: sum of (q - x)^2 in float32, q in float32
+//   ScoreFP8   FP8 E4M3 rows with one float32 scale s per row:
+//              sum of (q - s x)^2 in float32
+//   ScoreF32   float32 rows: sum of (q - x)^2 in float32
+//
+// Sequential semantics on a 64-lane wavefront.  Restart nodes are drawn one
+// at a time and tested, and the eager climb moves to the *first* improving
+// neighbour.  The kernel evaluates speculatively -- a window of 64 restart
+// candidates, or a whole neighbour list -- and commits only the prefix the
+// sequential rule evaluates (up to and including the first accepted restart
+// or improving neighbour, never past the budget).  Only committed
+// evaluations are counted, marked visited and offered to the result list,
+// so results, counts and evaluation order are those of the sequential
+// procedure on the same distances.
+//
+// Distances are handled as 32-bit patterns: int32 distances and non-negative
+// float32 distances both order like their bit patterns, so ballots, the
+// result list and keys (distance bits << 32 | id) are format independent.
+//
+// Candidates of a step are seen in two layouts: the "lane view" (candidate
+// c in lane c: sequential-order decisions with ballots) and the "group
+// view" (candidate p * SLOTS + g handled by lane group g in pass p: the
+// gathers and dot products; a group of G lanes reads one row, 16 bytes per
+// lane per load, CPL loads per lane).
+//
+// Latency.  A batch gives one wavefront per query, so its time is the
+// length of the slowest query's chain of dependent steps.  Every candidate's
+// adjacency row (LROW ids) is fetched with its point row and staged in LDS,
+// so a climb step costs one round trip to memory; and as soon as a step's
+// outcome is known the next step's gathers are issued, before this step's
+// bookkeeping (wavefront-local, no workgroup barrier), which then overlaps
+// the next round trip.
+#pragma once
+
+#include "common.h"
+#include "device.h"
+#include "internal.h"
+
+namespace knng {
+
+// ---- scoring formats -----------------------------------------------------------
+template <int G, int CPL>
+struct ScoreI8 {
+  static constexpr bool kScale = false;
+  v4i q[CPL];
+  int32_t qq;
+  __device__ void load(const SearchArgs& a, int32_t qi) {
+    const int sub = lane_id() % G;
+    int nrm = 0;
+    if (a.qvec) {
+      const int8_t* qr = (const int8_t*)a.qvec + (int64_t)qi * a.row_bytes;
+#pragma unroll
+      for (int pp = 0; pp < CPL; ++pp) {
+        int off = 16 * (sub + G * pp);
+        q[pp] = off < a.row_bytes ? *reinterpret_cast<const v4i*>(qr + off) : v4i{0, 0, 0, 0};
+      }
+    } else {
+      const uint8_t* qr = (const uint8_t*)a.qraw + (int64_t)qi * a.dim;
+#pragma unroll
+      for (int pp = 0; pp < CPL; ++pp) {
+        int off = 16 * (sub + G * pp);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int packed = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            int j = off + 4 * e + t;
+            int v = j < a.dim ? (int)qr[j] - 128 : 0;
+            packed |= (v & 0xff) << (8 * t);
+          }
+          q[pp][e] = packed;
+        }
+      }
+    }
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) nrm = __builtin_amdgcn_sdot4(q[pp][e], q[pp][e], nrm, false);
+    qq = group_sum<G>(nrm);
+  }
+  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+    int xx = 0, qx = 0;
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xx = __builtin_amdgcn_sdot4(x[pp][e], x[pp][e], xx, false);
+        qx = __builtin_amdgcn_sdot4(q[pp][e], x[pp][e], qx, false);
+      }
+    xx = group_sum<G>(xx);
+    qx = group_sum<G>(qx);
+    return (uint32_t)(qq + xx - 2 * qx);
+  }
+  // expansion test: keep r iff e_den (1 + d_r) <= e_num (1 + best)
+  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return !((int64_t)den * (1 + (int64_t)d) > (int64_t)num * (1 + (int64_t)best));
+  }
+};
+
+// float32 query coordinates for the chunks of a row format with EPC
+// coordinates per 16-byte chunk
+template <int G, int CPL, int EPC>
+__device__ __forceinline__ void load_query_f32(const SearchArgs& a, int32_t qi,
+                                               float (&q)[CPL][EPC]) {
+  const int sub = lane_id() % G;
+  const float* qr = (const float*)a.qraw + (int64_t)qi * a.dim;
+#pragma unroll
+  for (int pp = 0; pp < CPL; ++pp) {
+    int c0 = EPC * (sub + G * pp);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) q[pp][e] = c0 + e < a.dim ? qr[c0 + e] : 0.f;
+  }
+}
+
+__device__ __forceinline__ bool keep_f32(uint32_t d, uint32_t best, int num, int den) {
+  return !((float)den * (1.f + __uint_as_float(d)) > (float)num * (1.f + __uint_as_float(best)));
+}
+
+template <int G, int CPL>
+struct ScoreBF16 {
+  static constexpr bool kScale = false;
+  float q[CPL][8];
+  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 8>(a, qi, q); }
+  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+    float s = 0.f;
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t w = (uint32_t)x[pp][e];
+        float d0 = q[pp][2 * e] - bf16_lo(w);
+        float d1 = q[pp][2 * e + 1] - bf16_hi(w);
+        s = fmaf(d0, d0, s);
+        s = fmaf(d1, d1, s);
+      }
+    return __float_as_uint(group_sum<G>(s));
+  }
+  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return keep_f32(d, best, num, den);
+  }
+};
+
+// FP8 rows hold codes v with x ~ s v; the score is sum of (q - s v)^2.
+template <int G, int CPL>
+struct ScoreFP8 {
+  static constexpr bool kScale = true;
+  float q[CPL][16];
+  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 16>(a, qi, q); }
+  __device__ uint32_t dist(const v4i (&x)[CPL], float scale) const {
+    float s = 0.f;
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t w = (uint32_t)x[pp][e];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float d = __builtin_fmaf(-scale, e4m3_to_f32((w >> (8 * t)) & 0xffu), q[pp][4 * e + t]);
+          s = __builtin_fmaf(d, d, s);
+        }
+      }
+    return __float_as_uint(group_sum<G>(s));
+  }
+  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return keep_f32(d, best, num, den);
+  }
+};
+
+template <int G, int CPL>
+struct ScoreF32 {
+  static constexpr bool kScale = false;
+  float q[CPL][4];
+  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 4>(a, qi, q); }
+  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+    float s = 0.f;
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float d0 = q[pp][e] - __int_as_float(x[pp][e]);
+        s = fmaf(d0, d0, s);
+      }
+    return __float_as_uint(group_sum<G>(s));
+  }
+  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return keep_f32(d, best, num, den);
+  }
+};
+
+// ---- the search ----------------------------------------------------------------
+// CCPL > 0 (float graphs): the kept candidates are re-ranked by the float32
+// distance of stored float distances (CCPL chunks per lane of a 16-lane
+// group, CPB passes in flight) and the k best by that distance are the
+// result.
+template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB>
+__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint64_t tk_c[WAVE], tk_r[WAVE], tk_o[WAVE];
+  constexpr int SLOTS = WAVE / G;
+  constexpr bool LISTS = LROW > 0;
+  constexpr int LCH = LISTS ? LROW / 4 : 1;       // 16-byte chunks of a staged row
+  constexpr int LCPL = (LCH + G - 1) / G;         // list chunks per lane
+  const int lane = threadIdx.x;
+  const int slot = lane / G;
+  const int sub = lane % G;
+  const uint32_t mmask = a.m_mod - 1u;
+  const uint32_t n = (uint32_t)a.n;
+  int32_t* lists = reinterpret_cast<int32_t*>(lds + (GVIS ? 0 : a.vis_words_pad));
+  const char* rows = (const char*)a.vec;
+
+  for (int32_t qi = blockIdx.x; qi < a.m; qi += gridDim.x) {
+    uint32_t* vis = GVIS ? a.gvis + (int64_t)blockIdx.x * a.vis_words_pad : lds;
+    if (GVIS) {
+      for (int w = lane * 4; w < a.vis_words_pad; w += WAVE * 4)
+        *reinterpret_cast<v4i*>(vis + w) = v4i{0, 0, 0, 0};
+      __threadfence();
+    } else {
+      for (int w = lane; w < a.vis_words; w += WAVE) vis[w] = 0u;
+    }
+    __syncthreads();
+
+    Score sc;
+    sc.load(a, qi);
+    const uint64_t key = a.keys ? a.keys[qi] : a.key_base + (uint64_t)qi;
+    const Lcg lcg = restart_lcg(a.seed, key, a.m_mod);
+
+    // lane j holds the map x -> A x + C of j LCG steps (lane 0: identity)
+    uint32_t Ai = lcg.a, Ci = lcg.c;   // inclusive: lane + 1 steps
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+      uint32_t A2 = shfl_u32(Ai, lane >= off ? lane - off : lane);
+      uint32_t C2 = shfl_u32(Ci, lane >= off ? lane - off : lane);
+      if (lane >= off) {
+        Ci = Ai * C2 + Ci;
+        Ai = Ai * A2;
+      }
+    }
+    uint32_t Aj = shfl_u32(Ai, lane > 0 ? lane - 1 : 0);
+    uint32_t Cj = shfl_u32(Ci, lane > 0 ? lane - 1 : 0);
+    if (lane == 0) {
+      Aj = 1u;
+      Cj = 0u;
+    }
+    uint32_t Ag[G], Cg[G];           // the same for this lane's group candidates
+#pragma unroll
+    for (int p = 0; p < G; ++p) {
+      Ag[p] = G == 1 ? Aj : shfl_u32(Aj, p * SLOTS + slot);
+      Cg[p] = G == 1 ? Cj : shfl_u32(Cj, p * SLOTS + slot);
+    }
+
+    uint64_t rk = KEY_INF;          // result list: lane j < kk holds the j-th best
+    uint64_t kth = KEY_INF;         // (uniform) the list's kk-th key
+    uint32_t best = 0xffffffffu;    // (uniform) best distance bits so far
+    const int kk = a.keep;          // entries kept (k, or more before a re-rank)
+    int evals = 0;
+    int list_reads = 0;             // neighbour lists scanned by the climb
+    uint32_t P = 0;                 // permutation positions consumed
+    uint32_t xP = lcg.x0;           // value at position P
+    uint32_t dcur = 0;
+    bool climbing = false;
+    const int64_t trace_base = (int64_t)qi * a.trace_stride;
+
+    int32_t cidL = -1;              // lane view
+    uint32_t xL = 0;
+    int32_t cidG[G];                // group view
+    v4i xv[G][CPL];
+    v4i lv[G][LCPL];
+    float sv[G];
+
+    auto window = [&]() {
+      xL = (Aj * xP + Cj) & mmask;
+      cidL = (P + (uint32_t)lane < a.m_mod && xL < n) ? (int32_t)xL : -1;
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        const uint32_t c = (uint32_t)(p * SLOTS + slot);
+        const uint32_t xg = (Ag[p] * xP + Cg[p]) & mmask;
+        cidG[p] = (P + c < a.m_mod && xg < n) ? (int32_t)xg : -1;
+      }
+    };
+    auto issue = [&]() {
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        const bool ok = cidG[p] >= 0;
+        const char* row = rows + (int64_t)(ok ? cidG[p] : 0) * a.row_bytes;
+#pragma unroll
+        for (int pp = 0; pp < CPL; ++pp) {
+          const int off = 16 * (sub + G * pp);
+          if (ok && off < a.row_bytes)
+            xv[p][pp] = *reinterpret_cast<const v4i*>(row + off);
+          else
+            xv[p][pp] = v4i{0, 0, 0, 0};
+        }
+        if (Score::kScale) sv[p] = ok ? a.scale[cidG[p]] : 0.f;
+        if (LISTS) {
+#pragma unroll
+          for (int lc = 0; lc < LCPL; ++lc) {
+            const int chunk = sub + G * lc;
+            if (ok && chunk < LCH)
+              lv[p][lc] = *reinterpret_cast<const v4i*>(a.nbr_ids + (int64_t)cidG[p] * a.k_pad +
+                                                        4 * chunk);
+          }
+        }
+      }
+    };
+
+    bool done = a.B <= 0;
+    if (!done) {
+      window();
+      issue();
+    }
+    while (!done) {
+      // visited probe of the lane-view candidate while the gathers fly
+      const bool seen = GVIS ? gbit_test(vis, cidL >= 0 ? cidL : 0)
+                             : bit_test(vis, cidL >= 0 ? cidL : 0);
+      // distances of the group-view candidates; stage their adjacency rows
+      uint32_t dg[G];
+#pragma unroll
+      for (int p = 0; p < G; ++p) {
+        const int c = p * SLOTS + slot;
+        if (LISTS) {
+#pragma unroll
+          for (int lc = 0; lc < LCPL; ++lc) {
+            const int chunk = sub + G * lc;
+            if (cidG[p] >= 0 && chunk < LCH)
+              *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[p][lc];
+          }
+        }
+        const uint32_t dd = sc.dist(xv[p], Score::kScale ? sv[p] : 0.f);
+        dg[p] = cidG[p] >= 0 ? dd : 0xffffffffu;
+      }
+      uint32_t d = dg[0];
+      if (G > 1) {
+        d = 0xffffffffu;
+#pragma unroll
+        for (int p = 0; p < G; ++p) {
+          const int j = lane - p * SLOTS;
+          const bool mine = j >= 0 && j < SLOTS;
+          const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? j * G : 0);
+          if (mine) d = got;
+        }
+      }
+      const bool valid = cidL >= 0 && !seen;
+
+      // the sequential rule on this step's candidates
+      const uint64_t V = ballot(valid);
+      uint64_t S;                   // the lane the sequential rule stops at
+      if (!climbing) {
+        // Expansion test (similarity 1/(1+d) below s_max / e).  A restart
+        // that is rejected is never closer than the best so far, so a
+        // candidate is tested against the best before the window, or its
+        // own distance if that is smaller.
+        const uint32_t bt = d < best ? d : best;
+        S = ballot(valid && Score::keep(d, bt, a.e_num, a.e_den));
+      } else {
+        S = ballot(valid && d < dcur);
+      }
+      const int f = S ? __ffsll((long long)S) - 1 : WAVE;
+      uint64_t C = f < WAVE ? (V & ((2ull << f) - 1ull)) : V;
+      const int rem = a.B - evals;
+      bool stop = false;
+      if (__popcll(C) >= rem) {
+        const bool in = ((C >> lane) & 1ull) && rank_below(C) < rem;
+        C = ballot(in);
+        stop = true;
+      }
+      const bool mine = (C >> lane) & 1ull;
+      const int32_t cid_now = cidL;
+      const uint32_t d_now = d;
+
+      // the next step: decide its candidates and issue their gathers first
+      if (!stop) {
+        if (S) {
+          const int32_t cur = readlane_i32(cid_now, f);
+          dcur = (uint32_t)readlane_i32((int32_t)d_now, f);
+          if (!climbing) {
+            P += (uint32_t)f + 1u;
+            xP = (lcg.a * (uint32_t)cur + lcg.c) & mmask;
+            climbing = true;
+          }
+          if (LISTS) {
+            cidL = lane < a.k ? lists[f * LROW + lane] : -1;
+#pragma unroll
+            for (int p = 0; p < G; ++p) {
+              const int c = p * SLOTS + slot;
+              cidG[p] = c < a.k ? lists[f * LROW + c] : -1;
+            }
+          } else {
+            cidL = lane < a.k ? a.nbr_ids[(int64_t)cur * a.k_pad + lane] : -1;
+#pragma unroll
+            for (int p = 0; p < G; ++p) {
+              const int c = p * SLOTS + slot;
+              cidG[p] = G == 1 ? cidL : shfl_i32(cidL, c & 63);
+              if (c >= a.k) cidG[p] = -1;
+            }
+          }
+          ++list_reads;
+          issue();
+        } else if (!climbing) {
+          const uint32_t x63 = (uint32_t)readlane_i32((int32_t)xL, WAVE - 1);
+          P += WAVE;
+          xP = (lcg.a * x63 + lcg.c) & mmask;
+          if (P >= a.m_mod) {
+            done = true;
+          } else {
+            window();
+            issue();
+          }
+        } else {
+          climbing = false;        // local maximum: restart
+          window();
+          issue();
+        }
+      }
+
+      // bookkeeping of this step: visited, trace, result list, count
+      if (mine) atomicOr(&vis[cid_now >> 5], 1u << (cid_now & 31));
+      if (a.trace && mine) {
+        const int r = rank_below(C);
+        if (evals + r < a.trace_stride) a.trace[trace_base + evals + r] = cid_now;
+      }
+      const uint64_t key = make_key(d_now, cid_now);
+      if (ballot(mine && key < kth)) {
+        wave_topk_offer_ranked(rk, mine, key, kk, tk_c, tk_r, tk_o);
+        kth = readlane_u64(rk, kk - 1);
+        best = key_dist(readlane_u64(rk, 0));
+      }
+      evals += __popcll(C);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (stop) break;
+    }
+
+    if constexpr (CCPL > 0) {
+      float qc[CCPL][4];
+      canon_load_query<CCPL>((const float*)a.qraw + (int64_t)qi * a.dim, a.dim, qc);
+      const bool have = lane < kk && rk != KEY_INF;
+      const int32_t cid = have ? key_id(rk) : -1;
+      const uint32_t d32 =
+          canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride, a.master_chunks, cid);
+      const uint64_t nk = have ? make_key(d32, cid) : KEY_INF;
+      rk = KEY_INF;
+      wave_topk_offer_ranked(rk, have, nk, a.k, tk_c, tk_r, tk_o);
+    }
+    if (lane < a.out_stride) {
+      const bool have = lane < a.k && rk != KEY_INF;
+      a.out_ids[(int64_t)qi * a.out_stride + lane] = have ? key_id(rk) : -1;
+      a.out_d[(int64_t)qi * a.out_stride + lane] = have ? key_dist(rk) : a.pad_bits;
+    }
+    if (lane == 0) {
+      if (a.out_evals) a.out_evals[qi] = evals;
+      if (a.out_list_reads) a.out_list_reads[qi] = list_reads;
+      if (a.trace && evals < a.trace_stride) a.trace[trace_base + evals] = -1;
+    }
+    __syncthreads();
+  }
+}
+
+// Launch of one instantiation; LROW from the list stride (adjacency rows
+// of 16 or 32 ids are staged in LDS), GVIS from the caller's choice.
+template <class Score, int G, int CPL, int CCPL, int CPB>
+hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds) {
+  const bool gvis = a.gvis != nullptr;
+#define KNNG_SEARCH_GO(LR, GV)                                                              \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB>), dim3(grid), dim3(64), lds, \
+                     s, a)
+  if (a.k_pad == 16) {
+    if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
+  } else if (a.k_pad == 32) {
+    if (gvis) KNNG_SEARCH_GO(32, true); else KNNG_SEARCH_GO(32, false);
+  } else {
+    if (gvis) KNNG_SEARCH_GO(0, true); else KNNG_SEARCH_GO(0, false);
+  }
+#undef KNNG_SEARCH_GO
+  return hipGetLastError();
+}
+
+}  // namespace knng

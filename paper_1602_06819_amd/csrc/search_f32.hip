@@ -1,0 +1,21 @@
+// iGNNS launches for float graphs with float32 scoring rows, then the
+// float32 re-rank of the kept candidates.  Row shapes by dimension (16-byte
+// chunks of a scoring row; groups of G lanes read one row; CPL chunks per
+// lane):
+//   dim <= 64    16 chunks  G 4, CPL 4
+//   dim <= 128   32 chunks  G 8, CPL 4
+//   dim <= 256   64 chunks  G 16, CPL 4
+// The re-rank uses the layout of the stored float32 distance:
+// ceil(dim / 64) chunks per lane of a 16-lane group.
+#include "search.h"
+
+namespace knng {
+
+hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds) {
+  if (a.dim <= 64) return launch_search_t<ScoreF32<4, 4>, 4, 4, 1, 8>(a, s, grid, lds);
+  if (a.dim <= 128) return launch_search_t<ScoreF32<8, 4>, 8, 4, 2, 4>(a, s, grid, lds);
+  if (a.dim <= 256) return launch_search_t<ScoreF32<16, 4>, 16, 4, 4, 2>(a, s, grid, lds);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace knng

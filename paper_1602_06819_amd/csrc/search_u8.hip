@@ -1,0 +1,46 @@
+// iGNNS launches for int8 rows (uint8 graphs), and the format dispatch.
+#include "search.h"
+
+namespace knng {
+
+size_t search_lds_bytes(int64_t n, int k_pad, bool global_visited) {
+  size_t bytes = global_visited ? 0 : (size_t)round_up((n + 31) / 32, 4) * 4;
+  if (k_pad <= 32) bytes += (size_t)WAVE * k_pad * 4;   // staged adjacency rows
+  return bytes;
+}
+
+// One 16-byte chunk of a row per lane for rows of up to 64 bytes (a group
+// of lanes reads a whole row with one load instruction, so one instruction
+// fetches 64 / G rows); longer rows (up to 256 bytes): groups of 4 lanes,
+// up to 64 bytes per lane.
+static hipError_t launch_search_i8(const SearchArgs& a, hipStream_t s, unsigned grid,
+                                   size_t lds) {
+  const int chunks = a.row_bytes / 16;
+  if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1>(a, s, grid, lds);
+  if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1>(a, s, grid, lds);
+  if (chunks <= 4) return launch_search_t<ScoreI8<4, 1>, 4, 1, 0, 1>(a, s, grid, lds);
+  if (chunks <= 8) return launch_search_t<ScoreI8<4, 2>, 4, 2, 0, 1>(a, s, grid, lds);
+  if (chunks <= 16) return launch_search_t<ScoreI8<4, 4>, 4, 4, 0, 1>(a, s, grid, lds);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_search(const SearchArgs& a0, hipStream_t s) {
+  if (a0.m <= 0) return hipSuccess;
+  SearchArgs a = a0;
+  a.vis_words = (int32_t)((a.n + 31) / 32);
+  a.vis_words_pad = (int32_t)round_up(a.vis_words, 4);
+  const bool gvis = a.gvis != nullptr;
+  const size_t lds = search_lds_bytes(a.n, a.k_pad, gvis);
+  int64_t grid = a.m < 1048576 ? a.m : 1048576;
+  if (gvis && grid > a.gvis_slots) grid = a.gvis_slots;
+  if (grid < 1) return hipErrorInvalidValue;
+  switch (a.format) {
+    case ROW_I8: return launch_search_i8(a, s, (unsigned)grid, lds);
+    case ROW_BF16: return launch_search_bf16(a, s, (unsigned)grid, lds);
+    case ROW_FP8: return launch_search_fp8(a, s, (unsigned)grid, lds);
+    case ROW_F32: return launch_search_f32(a, s, (unsigned)grid, lds);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace knng

@@ -228,6 +228,18 @@ class KnnGraph:
         check(_lib.lib.knng_get_points(self._h, first, count, _ptr(x), _stream(stream)))
         return x
 
+    def rows(self, first: int = 0, count: int | None = None, stream=None):
+        """Stored scoring rows [count, row_bytes] (uint8 view of the bytes) and,
+        for FP8 scoring, the row scales [count]; otherwise (rows, None)."""
+        count = self.n - first if count is None else count
+        rb = int(_lib.lib.knng_row_bytes(self._h))
+        rows = torch.empty((count, rb), dtype=torch.uint8, device=self.device)
+        scale = (torch.empty(count, dtype=torch.float32, device=self.device)
+                 if self.cfg.score == "fp8" else None)
+        check(_lib.lib.knng_get_rows(self._h, first, count, _ptr(rows), _ptr(scale),
+                                     _stream(stream)))
+        return rows, scale
+
     def budget(self, n: int | None = None) -> int:
         n = self.n if n is None else n
         b = -(-n // self.cfg.speedup)

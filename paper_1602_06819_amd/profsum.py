@@ -24,7 +24,9 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SEARCH_SOURCES = ["csrc/online_u8.hip", "csrc/common.h", "csrc/internal.h"]
+SEARCH_SOURCES = ["csrc/search.h", "csrc/search_u8.hip", "csrc/device.h", "csrc/common.h",
+                  "csrc/internal.h"]
+SEARCH_KERNEL = "k_search<knng::ScoreI8"
 
 
 def search_kernel_hash() -> str:
@@ -105,13 +107,13 @@ def write_pmc(fetch_dir: str, write_dir: str, out: str, fetch_cmd: str, write_cm
     rows = {}
     for table, counter in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
         for (name, grid, cname), v in table.items():
-            if "k_search_u8" in name and cname == counter:
+            if SEARCH_KERNEL in name and cname == counter:
                 rows.setdefault(counter, {})[grid] = sum(v) / len(v)
     kib = 1024.0
     scale_f = copy_bytes / (max(copy_f[2]) * kib) if copy_f else None
     scale_w = copy_bytes / (max(copy_w[2]) * kib) if copy_w else None
     rec = {
-        "kernel": "k_search_u8",
+        "kernel": "k_search (int8 rows)",
         "source_hash": search_kernel_hash(),
         "fetch_command": fetch_cmd,
         "write_command": write_cmd,

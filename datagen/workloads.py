@@ -93,13 +93,13 @@ WORKLOADS: dict[str, Workload] = {
         name="f32-d128-n1m-b1024", kind="f32", dim=128, k=20, n_initial=1_000_000,
         n_insert=50_000, batch=1024, n_query=0, n_clusters=1000,
         mixture_seed=31, stream_seed=32, query_seed=33,
-        speedup=100, expansion_num=5, expansion_den=1, depth=2, score="bf16"),
+        speedup=5, expansion_num=3, expansion_den=2, depth=2, score="bf16"),
     # Serving: graph grows 1,000,000 -> 2,000,000, d=96 float32, 2,000 clusters, k=10.
     "serve-f32-d96-1m-2m": Workload(
         name="serve-f32-d96-1m-2m", kind="f32", dim=96, k=10, n_initial=1_000_000,
         n_insert=1_000_000, batch=4096, n_query=0, n_clusters=2000,
         mixture_seed=41, stream_seed=42, query_seed=43,
-        speedup=100, expansion_num=5, expansion_den=1, depth=2, score="bf16"),
+        speedup=10, expansion_num=3, expansion_den=2, depth=2, score="bf16"),
     # 500,000 initial float32 points, d=960, 500 clusters, heavy-tailed
     # per-dimension scales (log-normal, sigma 1), k=50; 20,000 inserts in
     # batches of 512; FP8 e4m3 scoring with per-vector scales.

@@ -198,6 +198,24 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m,
                        int32_t* ids_dev, void* d_dev, int32_t* evals_dev,
                        int32_t* list_reads_dev, hipStream_t stream);
 
+/*
+ * One serving epoch: a batch of b insert points and m read-only queries
+ * admitted together, all against the snapshot S of the n nodes present
+ * before the call.  Equivalent to knng_query(q) on S followed by
+ * knng_insert_batch(x) on S, with bit-identical results (the query keys are
+ * the next m query-sequence keys; the insert keys are the new ids), but the
+ * searches of both run in one launch.  Either part may be empty (b = 0 or
+ * m = 0); b <= max_batch, n + b <= capacity.
+ *  x_dev          [b][dim] insert points, device (may be NULL if b = 0).
+ *  q_dev          [m][dim] query points; q_ids_dev [m][k] int32 out,
+ *                 q_d_dev [m][k] int32 / float out, q_evals_dev [m] int32 out
+ *                 or NULL.
+ *  first_id_host  out: n, or NULL.   sims_dev [b] int32 out, or NULL.
+ */
+knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* q_dev,
+                       int64_t m, int32_t* q_ids_dev, void* q_d_dev, int32_t* q_evals_dev,
+                       int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream);
+
 /* Copy lists of nodes [first, first + count) out: ids_dev [count][k] int32,
  * d_dev [count][k] int32/float (either may be NULL). */
 knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,

@@ -311,12 +311,10 @@ knng_status make_handle(const knng_params* p, void* storage, size_t storage_byte
   return KNNG_OK;
 }
 
-// Search m queries -- ingested int8 rows (qvec, uint8 graphs) or raw points
-// (qraw: uint8 or float32) -- on the current graph.
-knng_status run_search(knng_graph* g, const int8_t* qvec, const void* qraw, int64_t m,
-                       const uint64_t* keys, uint64_t key_base, int32_t* out_ids,
-                       int32_t* out_d, int out_stride, int32_t* evals, int32_t* list_reads,
-                       int32_t* trace, int64_t trace_stride, int stage, hipStream_t stream) {
+// One search launch over one or two row groups (queries with their keys
+// and outputs) on the current graph.
+knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1, int stage,
+                       hipStream_t stream) {
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
   SearchArgs a{};
@@ -340,20 +338,10 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const void* qraw, int6
   a.e_num = g->p.expansion_num;
   a.e_den = g->p.expansion_den;
   a.seed = g->p.seed;
-  a.qvec = qvec;
-  a.qraw = qraw;
   a.dim = S.dim;
-  a.m = (int32_t)m;
-  a.keys = keys;
-  a.key_base = key_base;
-  a.out_ids = out_ids;
-  a.out_d = out_d;
-  a.out_stride = out_stride;
+  a.rows[0] = r0;
+  if (r1) a.rows[1] = *r1;
   a.pad_bits = (uint32_t)S.pad;
-  a.out_evals = evals;
-  a.out_list_reads = list_reads;
-  a.trace = trace;
-  a.trace_stride = trace_stride;
   if (search_sets_global(g->n)) {
     a.gvis = at<uint32_t>(g->ws, W.off_sets);
     a.gvis_slots = W.set_slots;
@@ -361,6 +349,45 @@ knng_status run_search(knng_graph* g, const int8_t* qvec, const void* qraw, int6
   Timed t(g, stage, stream);
   KNNG_TRY(launch_search(a, stream), "search launch");
   return KNNG_OK;
+}
+
+// Row group of a read-only search: raw points, caller's outputs.
+SearchRows query_rows(const void* q, int64_t m, const uint64_t* keys, uint64_t key_base,
+                      int32_t* ids, void* d, int stride, int32_t* evals, int32_t* list_reads,
+                      int32_t* trace, int64_t trace_stride) {
+  SearchRows r{};
+  r.qraw = q;
+  r.keys = keys;
+  r.key_base = key_base;
+  r.out_ids = ids;
+  r.out_d = (int32_t*)d;
+  r.out_stride = stride;
+  r.out_evals = evals;
+  r.out_list_reads = list_reads;
+  r.trace = trace;
+  r.trace_stride = trace_stride;
+  r.count = (int32_t)m;
+  return r;
+}
+
+// Row group of the points of an insert batch (stored at ids n .. n+b-1):
+// results into the workspace, key = id.
+SearchRows insert_rows(knng_graph* g, const void* x, int64_t b) {
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  SearchRows r{};
+  if (S.is_float)
+    r.qraw = x;
+  else
+    r.qvec = at<int8_t>(g->st, S.off_vec) + g->n * S.row_bytes;
+  r.key_base = (uint64_t)g->n;
+  r.out_ids = at<int32_t>(g->ws, W.off_res_ids);
+  r.out_d = at<int32_t>(g->ws, W.off_res_d);
+  r.out_stride = S.k_pad;
+  r.out_evals = at<int32_t>(g->ws, W.off_evals);
+  r.out_list_reads = at<int32_t>(g->ws, W.off_lreads);
+  r.count = (int32_t)b;
+  return r;
 }
 
 // Points -> stored rows (scoring rows, norms, float32 rows) at node ids
@@ -468,6 +495,103 @@ knng_status exact_lists(knng_graph* g, int64_t n, hipStream_t stream) {
   return KNNG_OK;
 }
 
+// Steps (ii)-(v) of an insert batch whose points are stored at ids
+// n .. n+b-1 and whose search results are in the workspace.
+knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int32_t* stats_dev,
+                                hipStream_t stream) {
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  const int64_t n = g->n;
+  int32_t* ids = at<int32_t>(g->st, S.off_ids);
+  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  int32_t* head = at<int32_t>(g->st, S.off_head);
+  int32_t* res_ids = at<int32_t>(g->ws, W.off_res_ids);
+  int32_t* res_d = at<int32_t>(g->ws, W.off_res_d);
+  int32_t* evals = at<int32_t>(g->ws, W.off_evals);
+  int32_t* lreads = at<int32_t>(g->ws, W.off_lreads);
+  int32_t* counters = at<int32_t>(g->ws, W.off_counters);
+  // rows of the distance evaluations after the search: int8 rows, or the
+  // float32 rows of float graphs
+  const int eval_format = S.is_float ? ROW_F32 : ROW_I8;
+  const char* eval_rows = S.is_float ? at<char>(g->st, S.off_master) : at<char>(g->st, S.off_vec);
+  const int eval_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
+
+  // (ii) lists of the new nodes: search result + batch peers
+  PeerArgs pa{};
+  pa.format = eval_format;
+  pa.bvec = eval_rows + n * eval_bytes;
+  pa.row_bytes = eval_bytes;
+  pa.dim = S.dim;
+  pa.b = (int32_t)b;
+  pa.id_base = (int32_t)n;
+  pa.k = S.k;
+  pa.k_pad = S.k_pad;
+  pa.res_ids = res_ids;
+  pa.res_d = res_d;
+  pa.list_ids = ids + n * S.k_pad;
+  pa.list_d = dist + n * S.k_pad;
+  pa.pad = S.pad;
+  {
+    Timed t(g, KNNG_STAGE_PEERS, stream);
+    KNNG_TRY(launch_peers(pa, stream), "peers launch");
+  }
+  // (iii) update proposals on the pre-batch lists
+  KNNG_TRY(launch_fill_i32(counters, 2, 0, stream), "fill");
+  UpdateArgs ua{};
+  ua.format = eval_format;
+  ua.vec = eval_rows;
+  ua.row_bytes = eval_bytes;
+  ua.dim = S.dim;
+  ua.nbr_ids = ids;
+  ua.nbr_d = dist;
+  ua.k = S.k;
+  ua.k_pad = S.k_pad;
+  ua.head = head;
+  ua.bvec = eval_rows + n * eval_bytes;
+  ua.b = (int32_t)b;
+  ua.id_base = (int32_t)n;
+  ua.res_ids = res_ids;
+  ua.res_d = res_d;
+  ua.depth = g->p.depth;
+  ua.props = at<Proposal>(g->ws, W.off_props);
+  ua.touched = at<int32_t>(g->ws, W.off_touched);
+  ua.counters = counters;
+  ua.evals = evals;
+  ua.list_reads = lreads;
+  ua.sims = sims_dev;
+  ua.stats = stats_dev;
+  ua.n = (int32_t)n;
+  ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
+  if (update_sets_global(n, ua.front_cap)) {
+    ua.gset = at<uint32_t>(g->ws, W.off_sets);
+    ua.gset_slots = W.set_slots;
+  }
+  {
+    Timed t(g, KNNG_STAGE_UPDATE, stream);
+    KNNG_TRY(launch_update(ua, stream), "update launch");
+  }
+  // (iv) merge proposals into the pre-batch lists
+  MergeArgs ma{};
+  ma.nbr_ids = ids;
+  ma.nbr_d = dist;
+  ma.k = S.k;
+  ma.k_pad = S.k_pad;
+  ma.head = head;
+  ma.props = ua.props;
+  ma.touched = ua.touched;
+  ma.counters = counters;
+  ma.max_touched = (int32_t)(b * W.props_per_point);
+  ma.pad = S.pad;
+  {
+    Timed t(g, KNNG_STAGE_MERGE, stream);
+    KNNG_TRY(launch_merge(ma, stream), "merge launch");
+  }
+  // (v)
+  g->n = n + b;
+  return KNNG_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -562,8 +686,9 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   if (trace_dev && trace_stride < budget(g->n, g->S.k, g->p.speedup))
     return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
                 (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
-  s = run_search(g, nullptr, q_dev, m, keys_dev, 0, ids_dev, (int32_t*)d_dev, g->S.k, evals_dev,
-                 list_reads_dev, trace_dev, trace_stride, KNNG_STAGE_QUERY, stream);
+  s = run_search(g, query_rows(q_dev, m, keys_dev, 0, ids_dev, d_dev, g->S.k, evals_dev,
+                                list_reads_dev, trace_dev, trace_stride),
+                 nullptr, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   return ok();
 }
@@ -578,9 +703,9 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
-  s = run_search(g, nullptr, q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount, ids_dev,
-                 (int32_t*)d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0,
-                 KNNG_STAGE_QUERY, stream);
+  s = run_search(g, query_rows(q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount,
+                                ids_dev, d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0),
+                 nullptr, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   g->qcount += m;
   return ok();
@@ -603,104 +728,49 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
   if (g->n + b > g->S.cap)
     return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
                 (long long)b, (long long)g->S.cap);
-  const StorageLayout& S = g->S;
-  const WorkspaceLayout& W = g->W;
-  const int64_t n = g->n;
-  int32_t* ids = at<int32_t>(g->st, S.off_ids);
-  int32_t* dist = at<int32_t>(g->st, S.off_dist);
-  int32_t* head = at<int32_t>(g->st, S.off_head);
-  int32_t* res_ids = at<int32_t>(g->ws, W.off_res_ids);
-  int32_t* res_d = at<int32_t>(g->ws, W.off_res_d);
-  int32_t* evals = at<int32_t>(g->ws, W.off_evals);
-  int32_t* lreads = at<int32_t>(g->ws, W.off_lreads);
-  int32_t* counters = at<int32_t>(g->ws, W.off_counters);
-  // rows of the distance evaluations after the search: int8 rows, or the
-  // float32 rows of float graphs
-  const int eval_format = S.is_float ? ROW_F32 : ROW_I8;
-  const char* eval_rows = S.is_float ? at<char>(g->st, S.off_master) : at<char>(g->st, S.off_vec);
-  const int eval_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
-
-  // (0) the new points, stored at their ids (not visible to the search,
-  //     which only reads nodes < n)
-  if ((s = ingest(g, x_dev, b, n, stream)) != KNNG_OK) return s;
+  knng_status st = ingest(g, x_dev, b, g->n, stream);
+  if (st != KNNG_OK) return st;
   // (i) iGNNS of every new point on the pre-batch graph, key = its id
-  const int8_t* bvec = S.is_float ? nullptr : at<int8_t>(g->st, S.off_vec) + n * S.row_bytes;
-  s = run_search(g, bvec, S.is_float ? x_dev : nullptr, b, nullptr, (uint64_t)n, res_ids, res_d,
-                 S.k_pad, evals, lreads, nullptr, 0, KNNG_STAGE_SEARCH, stream);
-  if (s != KNNG_OK) return s;
-  // (ii) lists of the new nodes: search result + batch peers
-  PeerArgs pa{};
-  pa.format = eval_format;
-  pa.bvec = eval_rows + n * eval_bytes;
-  pa.row_bytes = eval_bytes;
-  pa.dim = S.dim;
-  pa.b = (int32_t)b;
-  pa.id_base = (int32_t)n;
-  pa.k = S.k;
-  pa.k_pad = S.k_pad;
-  pa.res_ids = res_ids;
-  pa.res_d = res_d;
-  pa.list_ids = ids + n * S.k_pad;
-  pa.list_d = dist + n * S.k_pad;
-  pa.pad = S.pad;
-  {
-    Timed t(g, KNNG_STAGE_PEERS, stream);
-    KNNG_TRY(launch_peers(pa, stream), "peers launch");
-  }
-  // (iii) update proposals on the pre-batch lists
-  KNNG_TRY(launch_fill_i32(counters, 2, 0, stream), "fill");
-  UpdateArgs ua{};
-  ua.format = eval_format;
-  ua.vec = eval_rows;
-  ua.row_bytes = eval_bytes;
-  ua.dim = S.dim;
-  ua.nbr_ids = ids;
-  ua.nbr_d = dist;
-  ua.k = S.k;
-  ua.k_pad = S.k_pad;
-  ua.head = head;
-  ua.bvec = eval_rows + n * eval_bytes;
-  ua.b = (int32_t)b;
-  ua.id_base = (int32_t)n;
-  ua.res_ids = res_ids;
-  ua.res_d = res_d;
-  ua.depth = g->p.depth;
-  ua.props = at<Proposal>(g->ws, W.off_props);
-  ua.touched = at<int32_t>(g->ws, W.off_touched);
-  ua.counters = counters;
-  ua.evals = evals;
-  ua.list_reads = lreads;
-  ua.sims = sims_dev;
-  ua.stats = stats_dev;
-  ua.n = (int32_t)n;
-  ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
-  if (update_sets_global(n, ua.front_cap)) {
-    ua.gset = at<uint32_t>(g->ws, W.off_sets);
-    ua.gset_slots = W.set_slots;
-  }
-  {
-    Timed t(g, KNNG_STAGE_UPDATE, stream);
-    KNNG_TRY(launch_update(ua, stream), "update launch");
-  }
-  // (iv) merge proposals into the pre-batch lists
-  MergeArgs ma{};
-  ma.nbr_ids = ids;
-  ma.nbr_d = dist;
-  ma.k = S.k;
-  ma.k_pad = S.k_pad;
-  ma.head = head;
-  ma.props = ua.props;
-  ma.touched = ua.touched;
-  ma.counters = counters;
-  ma.max_touched = (int32_t)(b * W.props_per_point);
-  ma.pad = S.pad;
-  {
-    Timed t(g, KNNG_STAGE_MERGE, stream);
-    KNNG_TRY(launch_merge(ma, stream), "merge launch");
-  }
-  // (v)
+  if ((st = run_search(g, insert_rows(g, x_dev, b), nullptr, KNNG_STAGE_SEARCH, stream)) !=
+      KNNG_OK)
+    return st;
+  const int64_t n = g->n;
+  if ((st = insert_after_search(g, b, sims_dev, stats_dev, stream)) != KNNG_OK) return st;
   if (first_id_host) *first_id_host = n;
-  g->n = n + b;
+  return ok();
+}
+
+knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* q_dev,
+                       int64_t m, int32_t* q_ids_dev, void* q_d_dev, int32_t* q_evals_dev,
+                       int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (b < 0 || m < 0 || m >= ((int64_t)1 << 31))
+    return fail(KNNG_EINVAL, "b must be >= 0 and m in 0 .. 2^31-1");
+  if (b > 0 && (s = check_ptr(x_dev, "x_dev")) != KNNG_OK) return s;
+  if (m > 0) {
+    if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+    if ((s = check_ptr(q_ids_dev, "q_ids_dev")) != KNNG_OK) return s;
+    if ((s = check_ptr(q_d_dev, "q_d_dev")) != KNNG_OK) return s;
+  }
+  if (b > g->W.M)
+    return fail(KNNG_ECAPACITY, "batch %lld exceeds max_batch %lld", (long long)b,
+                (long long)g->W.M);
+  if (g->n + b > g->S.cap)
+    return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
+                (long long)b, (long long)g->S.cap);
+  const int64_t n = g->n;
+  if (first_id_host) *first_id_host = n;
+  if (b == 0 && m == 0) return ok();
+  if (b > 0 && (s = ingest(g, x_dev, b, n, stream)) != KNNG_OK) return s;
+  // one search launch: the batch's points (keys = ids) and the queries
+  // (keys 2^62 + query count), both on the snapshot of n nodes
+  SearchRows qr = query_rows(q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount,
+                             q_ids_dev, q_d_dev, g->S.k, q_evals_dev, nullptr, nullptr, 0);
+  SearchRows ir = insert_rows(g, x_dev, b);
+  if ((s = run_search(g, ir, &qr, KNNG_STAGE_SEARCH, stream)) != KNNG_OK) return s;
+  g->qcount += m;
+  if (b > 0 && (s = insert_after_search(g, b, sims_dev, nullptr, stream)) != KNNG_OK) return s;
   return ok();
 }
 

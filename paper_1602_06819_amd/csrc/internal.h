@@ -104,6 +104,18 @@ struct RerankArgs {
   int32_t* out_ids; int32_t* out_d; int out_stride;
 };
 
+// One group of search rows: its queries, restart keys and outputs.
+struct SearchRows {
+  const int8_t* qvec;    // uint8 graphs: ingested query rows [count][row_bytes], or null:
+  const void* qraw;      // raw queries [count][dim] (uint8 or float32)
+  const uint64_t* keys; uint64_t key_base;   // key = keys ? keys[i] : key_base + i
+  int32_t* out_ids; int32_t* out_d; int out_stride;
+  int32_t* out_evals;
+  int32_t* out_list_reads;   // neighbour lists read per query (may be null)
+  int32_t* trace; int64_t trace_stride;
+  int32_t count;
+};
+
 struct SearchArgs {
   int format;                              // RowFormat of vec
   const void* vec; int row_bytes;          // scoring rows
@@ -116,16 +128,12 @@ struct SearchArgs {
   uint32_t m_mod;        // permutation modulus m = 2^ceil(log2 n)
   int32_t e_num, e_den;
   uint64_t seed;
-  const int8_t* qvec;    // uint8 graphs: ingested query rows [m][row_bytes], or null:
-  const void* qraw;      // raw queries [m][dim] (uint8 or float32)
   int dim;
-  int32_t m;
-  const uint64_t* keys; uint64_t key_base;   // key = keys ? keys[i] : key_base + i
-  int32_t* out_ids; int32_t* out_d; int out_stride;
+  // rows [0, rows[0].count) come from group 0, the next rows[1].count from
+  // group 1 (one launch searches both on the same snapshot)
+  SearchRows rows[2];
+  int32_t m;             // rows[0].count + rows[1].count (set by the launcher)
   uint32_t pad_bits;     // distance padding of absent entries
-  int32_t* out_evals;
-  int32_t* out_list_reads;   // neighbour lists read per query (may be null)
-  int32_t* trace; int64_t trace_stride;
   uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
   int32_t vis_words, vis_words_pad;    // set by the launcher from n
 };

@@ -48,18 +48,18 @@ struct ScoreI8 {
   static constexpr bool kScale = false;
   v4i q[CPL];
   int32_t qq;
-  __device__ void load(const SearchArgs& a, int32_t qi) {
+  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     const int sub = lane_id() % G;
     int nrm = 0;
-    if (a.qvec) {
-      const int8_t* qr = (const int8_t*)a.qvec + (int64_t)qi * a.row_bytes;
+    if (r.qvec) {
+      const int8_t* qr = r.qvec + (int64_t)qi * a.row_bytes;
 #pragma unroll
       for (int pp = 0; pp < CPL; ++pp) {
         int off = 16 * (sub + G * pp);
         q[pp] = off < a.row_bytes ? *reinterpret_cast<const v4i*>(qr + off) : v4i{0, 0, 0, 0};
       }
     } else {
-      const uint8_t* qr = (const uint8_t*)a.qraw + (int64_t)qi * a.dim;
+      const uint8_t* qr = (const uint8_t*)r.qraw + (int64_t)qi * a.dim;
 #pragma unroll
       for (int pp = 0; pp < CPL; ++pp) {
         int off = 16 * (sub + G * pp);
@@ -104,10 +104,10 @@ struct ScoreI8 {
 // float32 query coordinates for the chunks of a row format with EPC
 // coordinates per 16-byte chunk
 template <int G, int CPL, int EPC>
-__device__ __forceinline__ void load_query_f32(const SearchArgs& a, int32_t qi,
-                                               float (&q)[CPL][EPC]) {
+__device__ __forceinline__ void load_query_f32(const SearchArgs& a, const SearchRows& r,
+                                               int32_t qi, float (&q)[CPL][EPC]) {
   const int sub = lane_id() % G;
-  const float* qr = (const float*)a.qraw + (int64_t)qi * a.dim;
+  const float* qr = (const float*)r.qraw + (int64_t)qi * a.dim;
 #pragma unroll
   for (int pp = 0; pp < CPL; ++pp) {
     int c0 = EPC * (sub + G * pp);
@@ -124,7 +124,9 @@ template <int G, int CPL>
 struct ScoreBF16 {
   static constexpr bool kScale = false;
   float q[CPL][8];
-  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 8>(a, qi, q); }
+  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+    load_query_f32<G, CPL, 8>(a, r, qi, q);
+  }
   __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
     float s = 0.f;
 #pragma unroll
@@ -149,7 +151,9 @@ template <int G, int CPL>
 struct ScoreFP8 {
   static constexpr bool kScale = true;
   float q[CPL][16];
-  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 16>(a, qi, q); }
+  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+    load_query_f32<G, CPL, 16>(a, r, qi, q);
+  }
   __device__ uint32_t dist(const v4i (&x)[CPL], float scale) const {
     float s = 0.f;
 #pragma unroll
@@ -174,7 +178,9 @@ template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kScale = false;
   float q[CPL][4];
-  __device__ void load(const SearchArgs& a, int32_t qi) { load_query_f32<G, CPL, 4>(a, qi, q); }
+  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+    load_query_f32<G, CPL, 4>(a, r, qi, q);
+  }
   __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
     float s = 0.f;
 #pragma unroll
@@ -212,7 +218,11 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   int32_t* lists = reinterpret_cast<int32_t*>(lds + (GVIS ? 0 : a.vis_words_pad));
   const char* rows = (const char*)a.vec;
 
-  for (int32_t qi = blockIdx.x; qi < a.m; qi += gridDim.x) {
+  for (int32_t qg = blockIdx.x; qg < a.m; qg += gridDim.x) {
+    // the row's group and index in it (uniform across the wavefront)
+    const bool g0 = qg < a.rows[0].count;
+    const SearchRows& R = g0 ? a.rows[0] : a.rows[1];
+    const int32_t qi = g0 ? qg : qg - a.rows[0].count;
     uint32_t* vis = GVIS ? a.gvis + (int64_t)blockIdx.x * a.vis_words_pad : lds;
     if (GVIS) {
       for (int w = lane * 4; w < a.vis_words_pad; w += WAVE * 4)
@@ -224,8 +234,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     __syncthreads();
 
     Score sc;
-    sc.load(a, qi);
-    const uint64_t key = a.keys ? a.keys[qi] : a.key_base + (uint64_t)qi;
+    sc.load(a, R, qi);
+    const uint64_t key = R.keys ? R.keys[qi] : R.key_base + (uint64_t)qi;
     const Lcg lcg = restart_lcg(a.seed, key, a.m_mod);
 
     // lane j holds the map x -> A x + C of j LCG steps (lane 0: identity)
@@ -262,7 +272,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     uint32_t xP = lcg.x0;           // value at position P
     uint32_t dcur = 0;
     bool climbing = false;
-    const int64_t trace_base = (int64_t)qi * a.trace_stride;
+    const int64_t trace_base = (int64_t)qi * R.trace_stride;
 
     int32_t cidL = -1;              // lane view
     uint32_t xL = 0;
@@ -418,9 +428,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 
       // bookkeeping of this step: visited, trace, result list, count
       if (mine) atomicOr(&vis[cid_now >> 5], 1u << (cid_now & 31));
-      if (a.trace && mine) {
+      if (R.trace && mine) {
         const int r = rank_below(C);
-        if (evals + r < a.trace_stride) a.trace[trace_base + evals + r] = cid_now;
+        if (evals + r < R.trace_stride) R.trace[trace_base + evals + r] = cid_now;
       }
       const uint64_t key = make_key(d_now, cid_now);
       if (ballot(mine && key < kth)) {
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 
     if constexpr (CCPL > 0) {
       float qc[CCPL][4];
-      canon_load_query<CCPL>((const float*)a.qraw + (int64_t)qi * a.dim, a.dim, qc);
+      canon_load_query<CCPL>((const float*)R.qraw + (int64_t)qi * a.dim, a.dim, qc);
       const bool have = lane < kk && rk != KEY_INF;
       const int32_t cid = have ? key_id(rk) : -1;
       const uint32_t d32 =
@@ -445,15 +455,15 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       rk = KEY_INF;
       wave_topk_offer_ranked(rk, have, nk, a.k, tk_c, tk_r, tk_o);
     }
-    if (lane < a.out_stride) {
+    if (lane < R.out_stride) {
       const bool have = lane < a.k && rk != KEY_INF;
-      a.out_ids[(int64_t)qi * a.out_stride + lane] = have ? key_id(rk) : -1;
-      a.out_d[(int64_t)qi * a.out_stride + lane] = have ? key_dist(rk) : a.pad_bits;
+      R.out_ids[(int64_t)qi * R.out_stride + lane] = have ? key_id(rk) : -1;
+      R.out_d[(int64_t)qi * R.out_stride + lane] = have ? key_dist(rk) : a.pad_bits;
     }
     if (lane == 0) {
-      if (a.out_evals) a.out_evals[qi] = evals;
-      if (a.out_list_reads) a.out_list_reads[qi] = list_reads;
-      if (a.trace && evals < a.trace_stride) a.trace[trace_base + evals] = -1;
+      if (R.out_evals) R.out_evals[qi] = evals;
+      if (R.out_list_reads) R.out_list_reads[qi] = list_reads;
+      if (R.trace && evals < R.trace_stride) R.trace[trace_base + evals] = -1;
     }
     __syncthreads();
   }

@@ -25,8 +25,9 @@ static hipError_t launch_search_i8(const SearchArgs& a, hipStream_t s, unsigned 
 }
 
 hipError_t launch_search(const SearchArgs& a0, hipStream_t s) {
-  if (a0.m <= 0) return hipSuccess;
   SearchArgs a = a0;
+  a.m = a.rows[0].count + a.rows[1].count;
+  if (a.m <= 0) return hipSuccess;
   a.vis_words = (int32_t)((a.n + 31) / 32);
   a.vis_words_pad = (int32_t)round_up(a.vis_words, 4);
   const bool gvis = a.gvis != nullptr;

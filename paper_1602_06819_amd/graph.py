@@ -167,6 +167,28 @@ class KnnGraph:
             return first.value, out, st
         return first.value, out
 
+    def epoch(self, x: torch.Tensor | None, q: torch.Tensor | None, sims: bool = False,
+              stream=None):
+        """One serving epoch on the current snapshot: queries q and the insert
+        batch x searched in one launch, then the batch's update.  Returns
+        (first id, sims or None, query ids, query d, query evals); the query
+        outputs are None when q is None."""
+        b = 0 if x is None else x.shape[0]
+        m = 0 if q is None else q.shape[0]
+        if b:
+            x = self._as_points(x)
+        if m:
+            q = self._as_points(q)
+        qi = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device) if m else None
+        qd = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device) if m else None
+        qe = torch.empty(m, dtype=torch.int32, device=self.device) if m else None
+        out = torch.empty(b, dtype=torch.int32, device=self.device) if (sims and b) else None
+        first = ctypes.c_int64(0)
+        check(_lib.lib.knng_epoch(self._h, _ptr(x) if b else None, b, _ptr(q) if m else None, m,
+                                  _ptr(qi), _ptr(qd), _ptr(qe), ctypes.byref(first), _ptr(out),
+                                  _stream(stream)))
+        return first.value, out, qi, qd, qe
+
     def search(self, q: torch.Tensor, keys: torch.Tensor, trace: bool = False,
                list_reads: bool = False, stream=None):
         """Raw iGNNS with explicit restart keys; returns (ids, d, evals, trace)

@@ -39,16 +39,29 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every HIP source and link the shared library; returns its path."""
+def _newest_header() -> float:
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads.append(os.path.join(ROOT, "include", "knng.h"))
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every HIP source and link the shared library; returns its path.
+    With ``incremental``, objects newer than their source and every header
+    are kept."""
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
     cmds = []
+    newest_h = _newest_header()
     for src in sources():
         obj = os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o")
         objs.append(obj)
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(src) and t > newest_h:
+                continue
         cmds.append([hipcc, *HIP_FLAGS, *inc, "-c", src, "-o", obj])
     jobs = jobs or min(len(cmds), os.cpu_count() or 4, 16)
 
@@ -60,6 +73,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
         return r
 
+    jobs = max(jobs, 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(run, cmds))
     tmp = LIB_PATH + ".tmp"
@@ -69,4 +83,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -321,7 +321,7 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.format = S.format;
   a.vec = at<char>(g->st, S.off_vec);
   a.row_bytes = S.row_bytes;
-  a.scale = S.format == ROW_FP8 ? at<float>(g->st, S.off_scale) : nullptr;
+  a.side = S.format == ROW_FP8 ? at<uint32_t>(g->st, S.off_scale) : nullptr;
   if (S.is_float) {
     a.master = at<float>(g->st, S.off_master);
     a.master_stride = S.mstride;

@@ -119,7 +119,7 @@ struct SearchRows {
 struct SearchArgs {
   int format;                              // RowFormat of vec
   const void* vec; int row_bytes;          // scoring rows
-  const float* scale;                      // FP8 row scales
+  const uint32_t* side;                    // per-row value: int8 norms, FP8 scales
   const float* master; int master_stride; int master_chunks;   // float graphs (re-rank)
   const int32_t* nbr_ids; int k, k_pad;
   int keep;              // result entries kept by the search (k, more before a re-rank)

@@ -43,9 +43,11 @@
 namespace knng {
 
 // ---- scoring formats -----------------------------------------------------------
+// |x|^2 is recomputed from the row (a stored norm would be one more gather
+// on every candidate's critical path).
 template <int G, int CPL>
 struct ScoreI8 {
-  static constexpr bool kScale = false;
+  static constexpr bool kSide = false;
   v4i q[CPL];
   int32_t qq;
   __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
@@ -82,7 +84,7 @@ struct ScoreI8 {
       for (int e = 0; e < 4; ++e) nrm = __builtin_amdgcn_sdot4(q[pp][e], q[pp][e], nrm, false);
     qq = group_sum<G>(nrm);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     int xx = 0, qx = 0;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -122,12 +124,12 @@ __device__ __forceinline__ bool keep_f32(uint32_t d, uint32_t best, int num, int
 
 template <int G, int CPL>
 struct ScoreBF16 {
-  static constexpr bool kScale = false;
+  static constexpr bool kSide = false;
   float q[CPL][8];
   __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 8>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     float s = 0.f;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -149,12 +151,13 @@ struct ScoreBF16 {
 // FP8 rows hold codes v with x ~ s v; the score is sum of (q - s v)^2.
 template <int G, int CPL>
 struct ScoreFP8 {
-  static constexpr bool kScale = true;
+  static constexpr bool kSide = true;    // the row scale
   float q[CPL][16];
   __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 16>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], float scale) const {
+  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t side) const {
+    const float scale = __uint_as_float(side);
     float s = 0.f;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -176,12 +179,12 @@ struct ScoreFP8 {
 
 template <int G, int CPL>
 struct ScoreF32 {
-  static constexpr bool kScale = false;
+  static constexpr bool kSide = false;
   float q[CPL][4];
   __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], float) const {
+  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     float s = 0.f;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     int32_t cidG[G];                // group view
     v4i xv[G][CPL];
     v4i lv[G][LCPL];
-    float sv[G];
+    uint32_t sv[G];                 // per-row side value (norm or scale)
 
     auto window = [&]() {
       xL = (Aj * xP + Cj) & mmask;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
           else
             xv[p][pp] = v4i{0, 0, 0, 0};
         }
-        if (Score::kScale) sv[p] = ok ? a.scale[cidG[p]] : 0.f;
+        if (Score::kSide) sv[p] = ok ? a.side[cidG[p]] : 0u;
         if (LISTS) {
 #pragma unroll
           for (int lc = 0; lc < LCPL; ++lc) {
@@ -317,19 +320,29 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       }
     };
 
+    // A list scan whose k candidates fit one pass is decided in the group
+    // view itself ("spaced": candidate c owned by lane c * G), without
+    // moving distances to the lane view.
+    const bool climb_spaced = G > 1 && (a.k + SLOTS - 1) / SLOTS == 1;
+
     bool done = a.B <= 0;
     if (!done) {
       window();
       issue();
     }
     while (!done) {
-      // visited probe of the lane-view candidate while the gathers fly
-      const bool seen = GVIS ? gbit_test(vis, cidL >= 0 ? cidL : 0)
-                             : bit_test(vis, cidL >= 0 ? cidL : 0);
-      // distances of the group-view candidates; stage their adjacency rows
+      const bool spaced = climbing && climb_spaced;
+      const int32_t cand = spaced ? cidG[0] : cidL;   // this lane's candidate
+      const bool owner = !spaced || sub == 0;
+      // visited probe of this lane's candidate while the gathers fly
+      const bool seen = GVIS ? gbit_test(vis, cand >= 0 ? cand : 0)
+                             : bit_test(vis, cand >= 0 ? cand : 0);
+      // distances of the group-view candidates; stage their adjacency rows.
+      // A list scan has at most k candidates: when they fit in fewer passes
+      // than G, only those passes are computed.
       uint32_t dg[G];
-#pragma unroll
-      for (int p = 0; p < G; ++p) {
+      uint32_t d = 0xffffffffu;
+      auto pass = [&](int p) {
         const int c = p * SLOTS + slot;
         if (LISTS) {
 #pragma unroll
@@ -339,21 +352,32 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
               *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[p][lc];
           }
         }
-        const uint32_t dd = sc.dist(xv[p], Score::kScale ? sv[p] : 0.f);
+        const uint32_t dd = sc.dist(xv[p], Score::kSide ? sv[p] : 0u);
         dg[p] = cidG[p] >= 0 ? dd : 0xffffffffu;
-      }
-      uint32_t d = dg[0];
-      if (G > 1) {
-        d = 0xffffffffu;
+      };
+      auto to_lane = [&](int p) {
+        const int j = lane - p * SLOTS;
+        const bool mine = j >= 0 && j < SLOTS;
+        const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? j * G : 0);
+        if (mine) d = got;
+      };
+      const int act = climbing ? (a.k + SLOTS - 1) / SLOTS : G;
+      if (G == 1) {
+        pass(0);
+        d = dg[0];
+      } else if (act == 1) {
+        pass(0);
+        if (spaced)
+          d = dg[0];
+        else
+          to_lane(0);
+      } else {
 #pragma unroll
-        for (int p = 0; p < G; ++p) {
-          const int j = lane - p * SLOTS;
-          const bool mine = j >= 0 && j < SLOTS;
-          const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? j * G : 0);
-          if (mine) d = got;
-        }
+        for (int p = 0; p < G; ++p) pass(p);
+#pragma unroll
+        for (int p = 0; p < G; ++p) to_lane(p);
       }
-      const bool valid = cidL >= 0 && !seen;
+      const bool valid = owner && cand >= 0 && !seen;
 
       // the sequential rule on this step's candidates
       const uint64_t V = ballot(valid);
@@ -378,7 +402,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         stop = true;
       }
       const bool mine = (C >> lane) & 1ull;
-      const int32_t cid_now = cidL;
+      const int32_t cid_now = cand;
       const uint32_t d_now = d;
 
       // the next step: decide its candidates and issue their gathers first
@@ -392,11 +416,12 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             climbing = true;
           }
           if (LISTS) {
-            cidL = lane < a.k ? lists[f * LROW + lane] : -1;
+            const int fc = spaced ? f / G : f;        // candidate index of lane f
+            if (!climb_spaced) cidL = lane < a.k ? lists[fc * LROW + lane] : -1;
 #pragma unroll
             for (int p = 0; p < G; ++p) {
               const int c = p * SLOTS + slot;
-              cidG[p] = c < a.k ? lists[f * LROW + c] : -1;
+              cidG[p] = c < a.k ? lists[fc * LROW + c] : -1;
             }
           } else {
             cidL = lane < a.k ? a.nbr_ids[(int64_t)cur * a.k_pad + lane] : -1;

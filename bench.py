@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--speedup", type=int, default=None, help="override the search speedup")
     ap.add_argument("--depth", type=int, default=None, help="override the update depth")
     ap.add_argument("--expansion", default=None, help="override e as num/den, e.g. 5/1")
+    ap.add_argument("--score", default=None, choices=["exact", "bf16", "fp8"],
+                    help="override the scoring rows of a float workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="points of the first batch the CPU oracle inserts")
@@ -131,6 +133,8 @@ def main():
     if args.expansion is not None:
         num, den = (int(v) for v in args.expansion.split("/"))
         w = w.scaled(expansion_num=num, expansion_den=den)
+    if args.score is not None:
+        w = w.scaled(score=args.score)
     speedup = args.speedup or w.speedup
     n0, b = w.n_initial, w.batch
     max_steps = len(w.batches())

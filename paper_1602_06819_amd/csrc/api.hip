@@ -176,8 +176,14 @@ knng_status check_params(const knng_params* p) {
     return fail(KNNG_EINVAL, "unknown score %d", p->score);
   if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
     return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
-  if (p->dim > 256)
-    return fail(KNNG_EINVAL, "this build supports dim <= 256 (got %d)", p->dim);
+  if (p->dtype == KNNG_U8 && p->dim > 256)
+    return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
+  if (p->dtype == KNNG_F32) {
+    const int lim = p->score == KNNG_SCORE_FP8 ? 1024 : p->score == KNNG_SCORE_BF16 ? 512 : 256;
+    if (p->dim > lim)
+      return fail(KNNG_EINVAL, "float data with this score supports dim <= %d (got %d)", lim,
+                  p->dim);
+  }
   if (p->capacity < 2 || p->capacity >= ((int64_t)1 << 31))
     return fail(KNNG_EINVAL, "capacity %lld outside 2 .. 2^31-1", (long long)p->capacity);
   if (p->max_batch < 1 || p->max_batch > p->capacity)

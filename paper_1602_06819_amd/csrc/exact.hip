@@ -172,6 +172,81 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
   }
 }
 
+// float32 rows longer than 16 slices (dimension above 256): the same tiles
+// with the coordinates in blocks of NCH 64-byte slices; the query operands
+// of each block are re-read per database tile (L1/L2 hits) and the products
+// accumulate across blocks.
+template <int DT, int KM, int NCH>
+__global__ __launch_bounds__(256) void k_exact_f32_long(ExactArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  const int32_t q = (int32_t)(blockIdx.x * 4 + wave) * 16 + col;
+  const int32_t qc = q < a.nq ? q : a.nq - 1;
+  const float* qrow = (const float*)a.qvec + (int64_t)qc * (a.row_bytes / 4);
+  const float qn = __uint_as_float(a.qnorm[qc]);
+  const int nkb = (a.row_bytes + 64 * NCH - 1) / (64 * NCH);
+  uint64_t L[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) L[j] = KEY_INF;
+
+  for (int32_t d0 = 0; d0 < a.nd; d0 += 16 * DT) {
+    v4f acc[DT];
+#pragma unroll
+    for (int dt = 0; dt < DT; ++dt) acc[dt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < nkb; ++kb) {
+      v4f bq[NCH];
+      v4f av[DT][NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int off = 64 * (kb * NCH + c) + 16 * grp;
+        bq[c] = off < a.row_bytes ? *reinterpret_cast<const v4f*>((const char*)qrow + off)
+                                  : v4f{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int dt = 0; dt < DT; ++dt) {
+        const int32_t r = d0 + 16 * dt + col;
+        const int32_t rc = r < a.nd ? r : a.nd - 1;
+        const char* drow = (const char*)a.dvec + (int64_t)rc * a.row_bytes;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int off = 64 * (kb * NCH + c) + 16 * grp;
+          av[dt][c] = off < a.row_bytes ? *reinterpret_cast<const v4f*>(drow + off)
+                                        : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+#pragma unroll
+      for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[dt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[dt][c][e], bq[c][e], acc[dt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int dt = 0; dt < DT; ++dt) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+        const int32_t on = orow < a.nd ? orow : a.nd - 1;
+        const float v = qn + __uint_as_float(a.dnorm[on]) - 2.f * acc[dt][rr];
+        const uint32_t dist = __float_as_uint(v > 0.f ? v : 0.f);
+        const bool ok = orow < a.nd &&
+                        !(a.exclude_self && a.d_id_base + orow == a.q_id_base + q);
+        const uint64_t key = ok ? make_key(dist, a.d_id_base + orow) : KEY_INF;
+        if (key < L[KM - 1]) reg_list_insert<KM>(L, key);
+      }
+    }
+  }
+  reg_list_merge_xor<KM>(L, 16);
+  reg_list_merge_xor<KM>(L, 32);
+  if (grp != 0 || q >= a.nq) return;
+  uint64_t* dst = a.cand + (int64_t)q * KM;
+#pragma unroll
+  for (int j = 0; j < KM; ++j) dst[j] = L[j];
+}
+
 // float32 re-rank of the candidate lists: one wavefront per query; lane
 // j < km takes candidate j, computes the stored float32 distance, and the
 // k best by (distance, id) are written.
@@ -274,7 +349,9 @@ static hipError_t launch_exact_f32_km(const ExactArgs& a, hipStream_t s) {
   if (nch <= 4) return launch_exact_t<true, QT, 2, KM, 4>(a, s);
   if (nch <= 8) return launch_exact_t<true, 1, 2, KM, 8>(a, s);
   if (nch <= 16) return launch_exact_t<true, 1, 1, KM, 16>(a, s);
-  return hipErrorInvalidValue;
+  dim3 grid((unsigned)((a.nq + 63) / 64));
+  hipLaunchKernelGGL((k_exact_f32_long<2, KM, 8>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_exact_f32(const ExactArgs& a, int km, hipStream_t s) {

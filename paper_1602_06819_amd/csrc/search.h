@@ -205,10 +205,18 @@ struct ScoreF32 {
 // distance of stored float distances (CCPL chunks per lane of a 16-lane
 // group, CPB passes in flight) and the k best by that distance are the
 // result.
-template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB>
+//
+// PB < G (long rows): a step's G passes are split into groups of PB passes
+// whose rows do not all fit in registers.  Group 0 is gathered with the
+// step's issue; while group j is scored, group j + 1 is gathered into the
+// other of two register buffers.
+template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[WAVE], tk_o[WAVE];
+  static_assert(G % PB == 0, "pass groups must divide the passes");
+  constexpr int NG = G / PB;                      // pass groups per step
+  constexpr int NB = NG > 1 ? 2 : 1;              // register buffers
   constexpr int SLOTS = WAVE / G;
   constexpr bool LISTS = LROW > 0;
   constexpr int LCH = LISTS ? LROW / 4 : 1;       // 16-byte chunks of a staged row
@@ -280,9 +288,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     int32_t cidL = -1;              // lane view
     uint32_t xL = 0;
     int32_t cidG[G];                // group view
-    v4i xv[G][CPL];
-    v4i lv[G][LCPL];
-    uint32_t sv[G];                 // per-row side value (norm or scale)
+    v4i xv[NB][PB][CPL];            // gathered rows, by buffer and pass in group
+    v4i lv[NB][PB][LCPL];           // gathered adjacency rows
+    uint32_t sv[NB][PB];            // per-row side value (FP8 scale)
 
     auto window = [&]() {
       xL = (Aj * xP + Cj) & mmask;
@@ -294,31 +302,33 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         cidG[p] = (P + c < a.m_mod && xg < n) ? (int32_t)xg : -1;
       }
     };
-    auto issue = [&]() {
+    auto issue_group = [&](int gi, int buf) {
 #pragma unroll
-      for (int p = 0; p < G; ++p) {
+      for (int q = 0; q < PB; ++q) {
+        const int p = gi * PB + q;
         const bool ok = cidG[p] >= 0;
         const char* row = rows + (int64_t)(ok ? cidG[p] : 0) * a.row_bytes;
 #pragma unroll
         for (int pp = 0; pp < CPL; ++pp) {
           const int off = 16 * (sub + G * pp);
           if (ok && off < a.row_bytes)
-            xv[p][pp] = *reinterpret_cast<const v4i*>(row + off);
+            xv[buf][q][pp] = *reinterpret_cast<const v4i*>(row + off);
           else
-            xv[p][pp] = v4i{0, 0, 0, 0};
+            xv[buf][q][pp] = v4i{0, 0, 0, 0};
         }
-        if (Score::kSide) sv[p] = ok ? a.side[cidG[p]] : 0u;
+        if (Score::kSide) sv[buf][q] = ok ? a.side[cidG[p]] : 0u;
         if (LISTS) {
 #pragma unroll
           for (int lc = 0; lc < LCPL; ++lc) {
             const int chunk = sub + G * lc;
             if (ok && chunk < LCH)
-              lv[p][lc] = *reinterpret_cast<const v4i*>(a.nbr_ids + (int64_t)cidG[p] * a.k_pad +
-                                                        4 * chunk);
+              lv[buf][q][lc] = *reinterpret_cast<const v4i*>(
+                  a.nbr_ids + (int64_t)cidG[p] * a.k_pad + 4 * chunk);
           }
         }
       }
     };
+    auto issue = [&]() { issue_group(0, 0); };
 
     // A list scan whose k candidates fit one pass is decided in the group
     // view itself ("spaced": candidate c owned by lane c * G), without
@@ -342,17 +352,17 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       // than G, only those passes are computed.
       uint32_t dg[G];
       uint32_t d = 0xffffffffu;
-      auto pass = [&](int p) {
+      auto pass = [&](int p, int buf, int q) {
         const int c = p * SLOTS + slot;
         if (LISTS) {
 #pragma unroll
           for (int lc = 0; lc < LCPL; ++lc) {
             const int chunk = sub + G * lc;
             if (cidG[p] >= 0 && chunk < LCH)
-              *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[p][lc];
+              *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[buf][q][lc];
           }
         }
-        const uint32_t dd = sc.dist(xv[p], Score::kSide ? sv[p] : 0u);
+        const uint32_t dd = sc.dist(xv[buf][q], Score::kSide ? sv[buf][q] : 0u);
         dg[p] = cidG[p] >= 0 ? dd : 0xffffffffu;
       };
       auto to_lane = [&](int p) {
@@ -363,17 +373,32 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       };
       const int act = climbing ? (a.k + SLOTS - 1) / SLOTS : G;
       if (G == 1) {
-        pass(0);
+        pass(0, 0, 0);
         d = dg[0];
       } else if (act == 1) {
-        pass(0);
+        pass(0, 0, 0);
         if (spaced)
           d = dg[0];
         else
           to_lane(0);
-      } else {
+      } else if (NG == 1) {
 #pragma unroll
-        for (int p = 0; p < G; ++p) pass(p);
+        for (int p = 0; p < G; ++p) pass(p, 0, p);
+#pragma unroll
+        for (int p = 0; p < G; ++p) to_lane(p);
+      } else {
+        const int ag = (act + PB - 1) / PB;       // pass groups holding candidates
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+          if (gi < ag) {
+            if (gi + 1 < ag) issue_group(gi + 1, (gi + 1) % NB);
+#pragma unroll
+            for (int q = 0; q < PB; ++q) pass(gi * PB + q, gi % NB, q);
+          } else {
+#pragma unroll
+            for (int q = 0; q < PB; ++q) dg[gi * PB + q] = 0xffffffffu;
+          }
+        }
 #pragma unroll
         for (int p = 0; p < G; ++p) to_lane(p);
       }
@@ -495,17 +520,20 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 }
 
 // Launch of one instantiation; LROW from the list stride (adjacency rows
-// of 16 or 32 ids are staged in LDS), GVIS from the caller's choice.
-template <class Score, int G, int CPL, int CCPL, int CPB>
-hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds) {
+// of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
+// `vis_lds` is the LDS of the visited set (0 when it is global).
+template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G>
+hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
   const bool gvis = a.gvis != nullptr;
-#define KNNG_SEARCH_GO(LR, GV)                                                              \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB>), dim3(grid), dim3(64), lds, \
-                     s, a)
+#define KNNG_SEARCH_GO(LR, GV)                                                                \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB>), dim3(grid), dim3(64), \
+                     vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.k_pad == 16) {
     if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
   } else if (a.k_pad == 32) {
     if (gvis) KNNG_SEARCH_GO(32, true); else KNNG_SEARCH_GO(32, false);
+  } else if (PB < G) {
+    if (gvis) KNNG_SEARCH_GO(64, true); else KNNG_SEARCH_GO(64, false);
   } else {
     if (gvis) KNNG_SEARCH_GO(0, true); else KNNG_SEARCH_GO(0, false);
   }

@@ -5,6 +5,7 @@
 //   dim <= 64     8 chunks  G 4, CPL 2
 //   dim <= 128   16 chunks  G 4, CPL 4
 //   dim <= 256   32 chunks  G 8, CPL 4
+//   dim <= 512   64 chunks  G 16, CPL 4, passes in groups of 4
 // The re-rank uses the layout of the stored float32 distance:
 // ceil(dim / 64) chunks per lane of a 16-lane group.
 #include "search.h"
@@ -15,6 +16,9 @@ hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid,
   if (a.dim <= 64) return launch_search_t<ScoreBF16<4, 2>, 4, 2, 1, 8>(a, s, grid, lds);
   if (a.dim <= 128) return launch_search_t<ScoreBF16<4, 4>, 4, 4, 2, 4>(a, s, grid, lds);
   if (a.dim <= 256) return launch_search_t<ScoreBF16<8, 4>, 8, 4, 4, 2>(a, s, grid, lds);
+  // long rows (up to 512 coordinates): 16 lanes per row, 4 chunks per
+  // lane, passes in groups of 4 with double-buffered gathers
+  if (a.dim <= 512) return launch_search_t<ScoreBF16<16, 4>, 16, 4, 8, 1, 4>(a, s, grid, lds);
   return hipErrorInvalidValue;
 }
 

@@ -5,6 +5,7 @@
 //   dim <= 64     4 chunks  G 4, CPL 1
 //   dim <= 128    8 chunks  G 4, CPL 2
 //   dim <= 256   16 chunks  G 4, CPL 4
+//   dim <= 1024  64 chunks  G 16, CPL 4, passes in groups of 2
 // The re-rank uses the layout of the stored float32 distance:
 // ceil(dim / 64) chunks per lane of a 16-lane group.
 #include "search.h"
@@ -15,6 +16,10 @@ hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, 
   if (a.dim <= 64) return launch_search_t<ScoreFP8<4, 1>, 4, 1, 1, 8>(a, s, grid, lds);
   if (a.dim <= 128) return launch_search_t<ScoreFP8<4, 2>, 4, 2, 2, 4>(a, s, grid, lds);
   if (a.dim <= 256) return launch_search_t<ScoreFP8<4, 4>, 4, 4, 4, 2>(a, s, grid, lds);
+  // long rows (up to 1024 coordinates): 16 lanes per row, 4 chunks per
+  // lane, passes in groups of 2 with double-buffered gathers
+  if (a.dim <= 512) return launch_search_t<ScoreFP8<16, 4>, 16, 4, 8, 1, 2>(a, s, grid, lds);
+  if (a.dim <= 1024) return launch_search_t<ScoreFP8<16, 4>, 16, 4, 16, 1, 2>(a, s, grid, lds);
   return hipErrorInvalidValue;
 }
 

@@ -3,10 +3,11 @@
 
 namespace knng {
 
+// LDS of the visited bitset (the staged adjacency rows are added per
+// instantiation by launch_search_t).
 size_t search_lds_bytes(int64_t n, int k_pad, bool global_visited) {
-  size_t bytes = global_visited ? 0 : (size_t)round_up((n + 31) / 32, 4) * 4;
-  if (k_pad <= 32) bytes += (size_t)WAVE * k_pad * 4;   // staged adjacency rows
-  return bytes;
+  (void)k_pad;
+  return global_visited ? 0 : (size_t)round_up((n + 31) / 32, 4) * 4;
 }
 
 // One 16-byte chunk of a row per lane for rows of up to 64 bytes (a group

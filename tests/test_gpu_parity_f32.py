@@ -100,10 +100,10 @@ def same_sequence(ref_d, got_d):
     return ok.all(axis=1)
 
 
-@pytest.mark.parametrize("score", ["bf16", "fp8", "exact"])
-def test_ingest_rows_match_quantizers(G, score):
+@pytest.mark.parametrize("score,dim", [("bf16", 40), ("fp8", 40), ("exact", 40),
+                                       ("bf16", 300), ("fp8", 960)])
+def test_ingest_rows_match_quantizers(G, score, dim):
     import torch
-    dim = 40
     X = f32_points(3, 300, dim) * 7.0
     X[5] = 0.0                                      # a zero row (FP8 scale 0)
     X[6, :4] = [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2 ** -11]   # rounding ties
@@ -112,13 +112,13 @@ def test_ingest_rows_match_quantizers(G, score):
     rows, scale = g.rows()
     rows = rows.cpu().numpy()
     if score == "bf16":
-        assert rows.shape[1] == 80
+        assert rows.shape[1] == -(-2 * dim // 16) * 16
         got = rows.view(np.uint16)[:, :dim]
         assert np.array_equal(got, O.quantize.bf16_bits(X))
         assert not rows.view(np.uint16)[:, dim:].any()
     elif score == "fp8":
         codes, s = O.quantize.fp8_rows(X)
-        assert rows.shape[1] == 48
+        assert rows.shape[1] == -(-dim // 16) * 16
         assert np.array_equal(scale.cpu().numpy(), s)
         assert np.array_equal(rows[:, :dim], codes)
         assert not rows[:, dim:].any()
@@ -127,12 +127,14 @@ def test_ingest_rows_match_quantizers(G, score):
     assert np.array_equal(g.points().cpu().numpy(), X)
 
 
-@pytest.mark.parametrize("n,dim,k", [(2500, 128, 20), (1100, 96, 10), (700, 37, 7), (300, 200, 50)])
-def test_exact_graph_float(G, n, dim, k):
+@pytest.mark.parametrize("n,dim,k,score", [(2500, 128, 20, "bf16"), (1100, 96, 10, "bf16"),
+                                           (700, 37, 7, "bf16"), (300, 200, 50, "bf16"),
+                                           (600, 960, 50, "fp8"), (900, 300, 20, "bf16")])
+def test_exact_graph_float(G, n, dim, k, score):
     import torch
     X = f32_points(11 + dim, n, dim)
     say(f"float exact graph n={n} d={dim} k={k}")
-    g = G.KnnGraph.build_exact(cfg_for(G, dim, k, n, 16), torch.from_numpy(X).cuda())
+    g = G.KnnGraph.build_exact(cfg_for(G, dim, k, n, 16, score=score), torch.from_numpy(X).cuda())
     ids, d = (t.cpu().numpy() for t in g.lists())
     check_lists(X, ids, d, self_ids=np.arange(n))
     worst = check_error(X, X, ids, d)
@@ -259,3 +261,43 @@ def test_query_float(G):
     rows = O.ExactRows(X[:n], k)
     ref = np.array([[dd for dd, _ in rows.row(q)] for q in X[n:]])
     assert same_sequence(ref, d.astype(np.float64)).all()
+
+
+@pytest.mark.parametrize("score,dim,k", [("fp8", 960, 50), ("bf16", 300, 20)])
+def test_long_rows_search_and_insert(G, score, dim, k):
+    """Rows longer than the register file holds for a whole step (pass
+    groups with double-buffered gathers): search invariants, the exhaustive
+    limit and batched inserts."""
+    import torch
+    n, m = 2000, 48
+    X = float_mixture(71, 10, dim, lognormal_dim_scale=1.0).sample(n + m + 200, 1071)
+    X = X.astype(np.float32)
+    base, Q, ins = X[:n], X[n:n + m], X[n + m:]
+    say(f"long rows score={score} d={dim} k={k}")
+    cfg = cfg_for(G, dim, k, n + 200, 128, score=score, speedup=4)
+    g = G.KnnGraph.build_exact(cfg, torch.from_numpy(base).cuda())
+    keys = torch.arange(900, 900 + m, dtype=torch.int64)
+    ids, d, ev, tr = (t.cpu().numpy() for t in g.search(torch.from_numpy(Q).cuda(), keys, trace=True))
+    B = g.budget()
+    assert np.all(ev == B)
+    for i in range(m):
+        seq = tr[i][tr[i] >= 0]
+        assert len(seq) == B and len(set(seq.tolist())) == B
+    check_lists(np.concatenate([base, Q]), ids, d, n_limit=n)
+    check_error(base, Q, ids, d)
+    g1 = G.KnnGraph.build_exact(cfg_for(G, dim, k, n, 64, score=score, speedup=1),
+                                torch.from_numpy(base).cuda())
+    ids1, d1, ev1, _ = g1.search(torch.from_numpy(Q).cuda(), keys)
+    rows = O.ExactRows(base, k)
+    exact = [rows.row(q) for q in Q]
+    rec = np.mean([len(set(ids1[i].cpu().numpy().tolist()) & {v for _, v in exact[i]}) / k
+                   for i in range(m)])
+    say(f"  exhaustive recall {rec:.4f}")
+    assert rec >= 0.97
+    g.insert(torch.from_numpy(ins[:128]).cuda())
+    g.insert(torch.from_numpy(ins[128:]).cuda())
+    Xall = np.concatenate([base, ins])
+    # the graph's node order is base then the inserted points
+    gi, gd = (t.cpu().numpy() for t in g.lists())
+    check_lists(Xall, gi, gd, self_ids=np.arange(len(Xall)))
+    check_error(Xall, Xall, gi, gd)

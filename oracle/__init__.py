@@ -23,6 +23,8 @@ silent are listed in each function's docstring):
 * the literal sequential transcription of Algorithms 1 and 2 (adds happen
   immediately), used to pin the batch form    -> :func:`online.insert_sequential_literal`
 * read-only k-nn query on the current graph   -> :func:`online.query`
+* GNNS, the baseline iGNNS improves on (fixed number of restarts, steepest
+  climb over every neighbour)                 -> :func:`gnns.gnns`
 * the number formats of the float path's scoring rows (bfloat16, FP8 E4M3
   with a row scale), from their definitions  -> :mod:`quantize`
 
@@ -42,6 +44,7 @@ from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
 from .exact import ExactRows, exact_graph, exact_graph_loops, exact_row  # noqa: F401
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
+from .gnns import gnns  # noqa: F401
 from . import quantize  # noqa: F401
 from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401
                      BatchResult, QUERY_KEY_BASE)

@@ -163,6 +163,21 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
                         int64_t trace_stride, hipStream_t stream);
 
 /*
+ * GNNS, the search iGNNS improves on (the baseline of the paper's
+ * comparison): every restart (drawn along the same keyed permutation) is
+ * climbed from; at each node every unvisited neighbour is evaluated and the
+ * search moves to the closest of them, by (distance, id), if it is strictly
+ * closer than the node; it stops after `restarts` restarts and their
+ * climbs, or after B(n) evaluations (set speedup = 1 for no budget).
+ * Evaluated nodes are never evaluated again.  Arguments as knng_search;
+ * uint8 graphs only (KNNG_EINVAL otherwise).  Read-only.
+ */
+knng_status knng_search_gnns(knng_graph* g, const void* q_dev, int64_t m,
+                             const uint64_t* keys_dev, int32_t restarts, int32_t* ids_dev,
+                             void* d_dev, int32_t* evals_dev, int32_t* trace_dev,
+                             int64_t trace_stride, hipStream_t stream);
+
+/*
  * Insert a batch of b points (Algorithms 1 and 2, batch form).  With n the
  * size before the call, the points get ids n .. n+b-1 and:
  *  (i)   each is searched with iGNNS on the pre-batch graph, key = its id;

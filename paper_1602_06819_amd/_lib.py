@@ -25,7 +25,7 @@ EXPORTED = [
     "knng_search", "knng_insert_batch", "knng_query", "knng_get_lists", "knng_get_points",
     "knng_size", "knng_query_count", "knng_last_error", "knng_destroy",
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
-    "knng_epoch",
+    "knng_epoch", "knng_search_gnns",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -100,6 +100,8 @@ def _load() -> ctypes.CDLL:
     lib.knng_get_rows.restype = ctypes.c_int
     lib.knng_epoch.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, P(i64), vp, vp]
     lib.knng_epoch.restype = ctypes.c_int
+    lib.knng_search_gnns.argtypes = [vp, vp, i64, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
+    lib.knng_search_gnns.restype = ctypes.c_int
     return lib
 
 

@@ -320,7 +320,7 @@ knng_status make_handle(const knng_params* p, void* storage, size_t storage_byte
 // One search launch over one or two row groups (queries with their keys
 // and outputs) on the current graph.
 knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1, int stage,
-                       hipStream_t stream) {
+                       hipStream_t stream, int32_t gnns_restarts = -1) {
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
   SearchArgs a{};
@@ -353,7 +353,12 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
     a.gvis_slots = W.set_slots;
   }
   Timed t(g, stage, stream);
-  KNNG_TRY(launch_search(a, stream), "search launch");
+  if (gnns_restarts >= 0) {
+    a.restarts = gnns_restarts;
+    KNNG_TRY(launch_search_gnns(a, stream), "search launch");
+  } else {
+    KNNG_TRY(launch_search(a, stream), "search launch");
+  }
   return KNNG_OK;
 }
 
@@ -695,6 +700,30 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
   s = run_search(g, query_rows(q_dev, m, keys_dev, 0, ids_dev, d_dev, g->S.k, evals_dev,
                                 list_reads_dev, trace_dev, trace_stride),
                  nullptr, KNNG_STAGE_QUERY, stream);
+  if (s != KNNG_OK) return s;
+  return ok();
+}
+
+knng_status knng_search_gnns(knng_graph* g, const void* q_dev, int64_t m,
+                             const uint64_t* keys_dev, int32_t restarts, int32_t* ids_dev,
+                             void* d_dev, int32_t* evals_dev, int32_t* trace_dev,
+                             int64_t trace_stride, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (m == 0) return ok();
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(KNNG_EINVAL, "m must be in 0 .. 2^31-1");
+  if (restarts < 0) return fail(KNNG_EINVAL, "restarts must be >= 0");
+  if (g->S.is_float) return fail(KNNG_EINVAL, "the GNNS baseline is built for uint8 graphs");
+  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  if (trace_dev && trace_stride < budget(g->n, g->S.k, g->p.speedup))
+    return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
+                (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
+  s = run_search(g, query_rows(q_dev, m, keys_dev, 0, ids_dev, d_dev, g->S.k, evals_dev,
+                                nullptr, trace_dev, trace_stride),
+                 nullptr, KNNG_STAGE_QUERY, stream, restarts);
   if (s != KNNG_OK) return s;
   return ok();
 }

@@ -136,6 +136,7 @@ struct SearchArgs {
   uint32_t pad_bits;     // distance padding of absent entries
   uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
   int32_t vis_words, vis_words_pad;    // set by the launcher from n
+  int32_t restarts;      // GNNS mode: number of restarts (launch_search_gnns)
 };
 
 struct PeerArgs {
@@ -190,6 +191,7 @@ hipError_t launch_rerank_f32(const RerankArgs& a, hipStream_t s);
 hipError_t launch_split_merge(const uint64_t* partial, int32_t nq, int32_t nsplit, int k,
                               int32_t* out_ids, int32_t* out_d, int out_stride, hipStream_t s);
 hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+hipError_t launch_search_gnns(const SearchArgs& a, hipStream_t s);
 hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);

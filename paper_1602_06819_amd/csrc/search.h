@@ -210,7 +210,14 @@ struct ScoreF32 {
 // whose rows do not all fit in registers.  Group 0 is gathered with the
 // step's issue; while group j is scored, group j + 1 is gathered into the
 // other of two register buffers.
-template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB>
+//
+// GNNS (the baseline of the comparison in the paper's evaluation): every
+// restart is climbed from, a list scan evaluates every unvisited neighbour
+// and moves to the closest of them if it is strictly closer than the
+// current node, and the search ends after a.restarts restarts and their
+// climbs (or at the budget).
+template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB,
+          bool GNNS = false>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[WAVE], tk_o[WAVE];
@@ -335,7 +342,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     // moving distances to the lane view.
     const bool climb_spaced = G > 1 && (a.k + SLOTS - 1) / SLOTS == 1;
 
-    bool done = a.B <= 0;
+    int restarts_used = 0;          // GNNS: restarts taken
+    bool done = a.B <= 0 || (GNNS && a.restarts <= 0);
     if (!done) {
       window();
       issue();
@@ -413,12 +421,20 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         // candidate is tested against the best before the window, or its
         // own distance if that is smaller.
         const uint32_t bt = d < best ? d : best;
-        S = ballot(valid && Score::keep(d, bt, a.e_num, a.e_den));
+        S = GNNS ? V : ballot(valid && Score::keep(d, bt, a.e_num, a.e_den));
+        if (GNNS && S) ++restarts_used;
+      } else if (GNNS) {
+        // steepest: the closest unvisited neighbour, if closer than current
+        uint64_t m = valid ? make_key(d, cand) : KEY_INF;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m = min_u64(m, shfl_xor_u64(m, off));
+        const bool better = m != KEY_INF && key_dist(m) < dcur;
+        S = better ? ballot(valid && make_key(d, cand) == m) : 0ull;
       } else {
         S = ballot(valid && d < dcur);
       }
       const int f = S ? __ffsll((long long)S) - 1 : WAVE;
-      uint64_t C = f < WAVE ? (V & ((2ull << f) - 1ull)) : V;
+      uint64_t C = (GNNS && climbing) ? V : (f < WAVE ? (V & ((2ull << f) - 1ull)) : V);
       const int rem = a.B - evals;
       bool stop = false;
       if (__popcll(C) >= rem) {
@@ -469,6 +485,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             window();
             issue();
           }
+        } else if (GNNS && restarts_used >= a.restarts) {
+          done = true;             // local maximum after the last restart
         } else {
           climbing = false;        // local maximum: restart
           window();
@@ -522,12 +540,12 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 // Launch of one instantiation; LROW from the list stride (adjacency rows
 // of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
 // `vis_lds` is the LDS of the visited set (0 when it is global).
-template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G>
+template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false>
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
   const bool gvis = a.gvis != nullptr;
-#define KNNG_SEARCH_GO(LR, GV)                                                                \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB>), dim3(grid), dim3(64), \
-                     vis_lds + (size_t)WAVE * (LR) * 4, s, a)
+#define KNNG_SEARCH_GO(LR, GV)                                                              \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS>), dim3(grid),   \
+                     dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.k_pad == 16) {
     if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
   } else if (a.k_pad == 32) {

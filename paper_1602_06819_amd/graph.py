@@ -211,6 +211,25 @@ class KnnGraph:
             return ids, d, ev, tr, lr
         return ids, d, ev, tr
 
+    def search_gnns(self, q: torch.Tensor, keys: torch.Tensor, restarts: int,
+                    trace: bool = False, stream=None):
+        """GNNS baseline search (fixed restarts, steepest climb); returns
+        (ids, d, evals, trace)."""
+        q = self._as_points(q)
+        m = q.shape[0]
+        keys = keys.to(device=self.device, dtype=torch.int64).contiguous()
+        ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
+        d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
+        ev = torch.empty(m, dtype=torch.int32, device=self.device)
+        tr = None
+        stride = 0
+        if trace:
+            stride = self.budget()
+            tr = torch.full((m, stride), -1, dtype=torch.int32, device=self.device)
+        check(_lib.lib.knng_search_gnns(self._h, _ptr(q), m, _ptr(keys), restarts, _ptr(ids),
+                                        _ptr(d), _ptr(ev), _ptr(tr), stride, _stream(stream)))
+        return ids, d, ev, tr
+
     def query(self, q: torch.Tensor, list_reads: bool = False, stream=None):
         """Read-only k-nn query; returns (ids, d, evals[, list_reads])."""
         q = self._as_points(q)

@@ -73,6 +73,15 @@ class Workload:
 
 
 WORKLOADS: dict[str, Workload] = {
+    # The paper's synthetic data set is a Gaussian mixture in R^3 (Section
+    # 8.1.1; its parameters are not given): 10 centres ~ N(0,1)^3, per-cluster
+    # sigma ~ U[0.05, 0.3], float32, k = 10.  Used by the experiment harness
+    # at the paper's sizes.
+    "f32-d3-gmm": Workload(
+        name="f32-d3-gmm", kind="f32", dim=3, k=10, n_initial=8000,
+        n_insert=16000, batch=1, n_query=1000, n_clusters=10,
+        mixture_seed=61, stream_seed=62, query_seed=63,
+        speedup=4, expansion_num=5, expansion_den=1, depth=2, score="exact"),
     # 2,000 initial uint8 points, d=16, 10 clusters (centres U[40,215], sigma
     # 12), squared L2, k=10; then 200 inserts one at a time.
     "u8-d16-n2k-b1": Workload(

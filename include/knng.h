@@ -85,10 +85,9 @@ typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } k
  *             restart node r is discarded iff
  *             den * (1 + d_r) > num * (1 + d_best), i.e. similarity
  *             1 / (1 + d) below s_max / e.
- *  depth      DEPTH of the Update procedure (Algorithm 2), 1 .. 8, such
- *             that the per-point processed set (2 (k + ... + k^depth) slots)
- *             and two level arrays (k^(depth-1) slots each) fit in 64 KiB.
- *             Supported: k = 10 up to depth 3, k = 50 up to depth 2.
+ *  depth      DEPTH of the Update procedure (Algorithm 2), 1 .. 8, with
+ *             k + k^2 + ... + k^depth <= 2^24 (the workspace holds that many
+ *             proposal slots per batch point; k = 10 allows depth 7).
  *  seed       seed of the restart permutations (see knng_search).
  */
 typedef struct {
@@ -170,7 +169,8 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
  * closer than the node; it stops after `restarts` restarts and their
  * climbs, or after B(n) evaluations (set speedup = 1 for no budget).
  * Evaluated nodes are never evaluated again.  Arguments as knng_search;
- * uint8 graphs only (KNNG_EINVAL otherwise).  Read-only.
+ * uint8 graphs, or float graphs with KNNG_SCORE_EXACT (float32 scoring;
+ * KNNG_EINVAL otherwise).  Read-only.
  */
 knng_status knng_search_gnns(knng_graph* g, const void* q_dev, int64_t m,
                              const uint64_t* keys_dev, int32_t restarts, int32_t* ids_dev,

@@ -154,8 +154,13 @@ int64_t set_bytes(int64_t n) { return round_up((n + 31) / 32, 4) * 4; }
 // Where the visited set of a search and the processed set of an update
 // live: LDS while they fit, else per-block bitsets in the workspace.
 bool search_sets_global(int64_t n) { return (size_t)set_bytes(n) > LDS_SET_LIMIT; }
+// The update's two level arrays live in LDS up to 32 KiB, else in the
+// workspace (one slice per block); its processed set in LDS while the set
+// and the arrays held there fit.
+bool update_fronts_global(int64_t front_cap) { return 8 * front_cap > 32768; }
 bool update_sets_global(int64_t n, int64_t front_cap) {
-  return (size_t)set_bytes(n) + 8 * (size_t)front_cap > LDS_LIMIT;
+  const size_t fronts = update_fronts_global(front_cap) ? 0 : 8 * (size_t)front_cap;
+  return (size_t)set_bytes(n) + fronts > LDS_LIMIT;
 }
 
 int row_format(const knng_params& p) {
@@ -192,9 +197,16 @@ knng_status check_params(const knng_params* p) {
   if (p->expansion_den < 1 || p->expansion_num <= p->expansion_den)
     return fail(KNNG_EINVAL, "expansion num/den must be > 1 with den >= 1");
   if (p->depth < 1 || p->depth > 8) return fail(KNNG_EINVAL, "depth must be 1 .. 8");
-  if (update_lds_bytes(0, update_sizes(p->k, p->depth).front_cap, true) > LDS_LIMIT - 4096)
-    return fail(KNNG_EINVAL, "depth %d with k %d needs level arrays larger than the LDS of "
-                             "one wavefront (k^(depth-1) too large)", p->depth, p->k);
+  {
+    double level = 1.0, total = 0.0;
+    for (int l = 1; l <= p->depth; ++l) {
+      level *= p->k;
+      total += level;
+    }
+    if (total > (double)(1 << 24))
+      return fail(KNNG_EINVAL, "depth %d with k %d: k + ... + k^depth exceeds 2^24 update "
+                               "slots per point", p->depth, p->k);
+  }
   return KNNG_OK;
 }
 
@@ -252,6 +264,8 @@ WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
   W.off_counters = take(cur, 256);
   W.off_partial = take(cur, (size_t)W.partial_lists * S.k_pad * 8);
   W.off_keys = take(cur, M * 8);
+  if (update_fronts_global(us.front_cap))
+    W.off_fronts = take(cur, M * 2 * (size_t)us.front_cap * 4);
   if (search_sets_global(S.cap) || update_sets_global(S.cap, us.front_cap)) {
     W.set_slots = W.M;
     W.set_words_pad = set_bytes(S.cap) / 4;
@@ -573,6 +587,7 @@ knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int
   ua.stats = stats_dev;
   ua.n = (int32_t)n;
   ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
+  if (update_fronts_global(ua.front_cap)) ua.gfront = at<int32_t>(g->ws, W.off_fronts);
   if (update_sets_global(n, ua.front_cap)) {
     ua.gset = at<uint32_t>(g->ws, W.off_sets);
     ua.gset_slots = W.set_slots;
@@ -713,7 +728,9 @@ knng_status knng_search_gnns(knng_graph* g, const void* q_dev, int64_t m,
   if (m == 0) return ok();
   if (m < 0 || m >= ((int64_t)1 << 31)) return fail(KNNG_EINVAL, "m must be in 0 .. 2^31-1");
   if (restarts < 0) return fail(KNNG_EINVAL, "restarts must be >= 0");
-  if (g->S.is_float) return fail(KNNG_EINVAL, "the GNNS baseline is built for uint8 graphs");
+  if (g->S.is_float && g->S.format != ROW_F32)
+    return fail(KNNG_EINVAL, "the GNNS baseline is built for uint8 graphs and float graphs "
+                             "with float32 scoring");
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;

@@ -47,6 +47,7 @@ struct StorageLayout {
 //   sets          visited / processed bitsets in global memory, one per
 //                 block, for graphs whose bitset does not fit in LDS
 //   cand          float exact graph: candidate keys of a chunk of nodes
+//   fronts        update level arrays that do not fit in LDS, per block
 struct WorkspaceLayout {
   int64_t M = 0;
   int64_t props_per_point = 0;
@@ -55,7 +56,7 @@ struct WorkspaceLayout {
   int64_t cand_rows = 0;
   size_t off_res_ids = 0, off_res_d = 0, off_evals = 0,
          off_upd = 0, off_lreads = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
-         off_keys = 0, off_sets = 0, off_cand = 0, total = 0;
+         off_keys = 0, off_sets = 0, off_cand = 0, off_fronts = 0, total = 0;
 };
 
 struct Proposal {
@@ -165,6 +166,7 @@ struct UpdateArgs {
   uint32_t* gset; int64_t gset_slots;             // global processed sets (null: LDS)
   int32_t set_words, set_words_pad;   // set by the launcher from n
   int front_cap;         // slots of one level array (largest expanded level)
+  int32_t* gfront;       // level arrays in global memory [b][2][front_cap] (null: LDS)
 };
 
 struct MergeArgs {
@@ -177,7 +179,7 @@ struct MergeArgs {
 
 // ---- LDS needs of the online kernels (bytes per wavefront) -------------------
 size_t search_lds_bytes(int64_t n, int k_pad, bool global_visited);
-size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set);
+size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set, bool global_front);
 constexpr size_t LDS_LIMIT = 65536;
 // Bitsets up to this size stay in LDS; larger graphs use global bitsets.
 constexpr size_t LDS_SET_LIMIT = 40960;
@@ -195,6 +197,8 @@ hipError_t launch_search_gnns(const SearchArgs& a, hipStream_t s);
 hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
+hipError_t launch_search_f32_gnns(const SearchArgs& a, hipStream_t s, unsigned grid,
+                                  size_t lds);
 hipError_t launch_peers(const PeerArgs& a, hipStream_t s);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);

@@ -184,7 +184,8 @@ template <class Eval, bool GSET>
 __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
   extern __shared__ uint32_t lds[];
   uint32_t* done_bits = GSET ? a.gset + (int64_t)blockIdx.x * a.set_words_pad : lds;
-  int32_t* front = reinterpret_cast<int32_t*>(lds + (GSET ? 0 : a.set_words_pad));
+  int32_t* front = a.gfront ? a.gfront + (int64_t)blockIdx.x * 2 * a.front_cap
+                           : reinterpret_cast<int32_t*>(lds + (GSET ? 0 : a.set_words_pad));
   int32_t* nxt = front + a.front_cap;
   __shared__ int32_t next_count;
   const int lane = threadIdx.x;
@@ -343,9 +344,9 @@ struct UpdateFn {
   }
 };
 
-size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set) {
+size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set, bool global_front) {
   size_t bytes = global_set ? 0 : (size_t)round_up((n + 31) / 32, 4) * 4;
-  return bytes + 2 * (size_t)front_cap * 4;
+  return bytes + (global_front ? 0 : 2 * (size_t)front_cap * 4);
 }
 
 hipError_t launch_peers(const PeerArgs& a, hipStream_t s) {
@@ -359,7 +360,7 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   b.set_words = (int32_t)((a.n + 31) / 32);
   b.set_words_pad = (int32_t)round_up(b.set_words, 4);
   if (b.gset && a.b > a.gset_slots) return hipErrorInvalidValue;
-  size_t lds = update_lds_bytes(a.n, a.front_cap, b.gset != nullptr);
+  size_t lds = update_lds_bytes(a.n, a.front_cap, b.gset != nullptr, b.gfront != nullptr);
   return dispatch_eval<UpdateFn>(a.format, a.row_bytes, b, s, dim3((unsigned)a.b), lds);
 }
 

@@ -41,7 +41,7 @@ hipError_t launch_search_gnns(const SearchArgs& a0, hipStream_t s) {
   SearchArgs a = a0;
   a.m = a.rows[0].count + a.rows[1].count;
   if (a.m <= 0) return hipSuccess;
-  if (a.format != ROW_I8) return hipErrorInvalidValue;
+  if (a.format != ROW_I8 && a.format != ROW_F32) return hipErrorInvalidValue;
   a.vis_words = (int32_t)((a.n + 31) / 32);
   a.vis_words_pad = (int32_t)round_up(a.vis_words, 4);
   const bool gvis = a.gvis != nullptr;
@@ -49,6 +49,7 @@ hipError_t launch_search_gnns(const SearchArgs& a0, hipStream_t s) {
   int64_t grid = a.m < 1048576 ? a.m : 1048576;
   if (gvis && grid > a.gvis_slots) grid = a.gvis_slots;
   if (grid < 1) return hipErrorInvalidValue;
+  if (a.format == ROW_F32) return launch_search_f32_gnns(a, s, (unsigned)grid, lds);
   return launch_search_i8_gnns(a, s, (unsigned)grid, lds);
 }
 

@@ -58,3 +58,25 @@ def test_gnns_bit_exact(G, dim, k, restarts, speedup):
         assert tr[j, :r.evals].tolist() == r.sequence, j
         assert ids[j, :len(r.pairs)].tolist() == [v for _, v in r.pairs], j
         assert d[j, :len(r.pairs)].tolist() == [dd for dd, _ in r.pairs], j
+
+
+def test_gnns_float32_follows_oracle(G):
+    """float32 scoring decides like the float64 oracle except at near ties."""
+    import torch
+    from datagen import float_mixture
+    n, dim, k, R = 3000, 3, 10, 6
+    X = float_mixture(83, 10, dim).sample(n + 100, 1083).astype(np.float32)
+    cfg = G.GraphConfig(dim=dim, k=k, capacity=n, max_batch=100, speedup=1, seed=99,
+                        dtype="f32", score="exact")
+    g = G.KnnGraph.build_exact(cfg, tensor(X[:n]))
+    keys = torch.arange(500, 600, dtype=torch.int64)
+    ids, d, ev, tr = (t.cpu().numpy() for t in g.search_gnns(tensor(X[n:]), keys, R, trace=True))
+    oi, od = O.exact_graph(X[:n], k)
+    og = O.OracleGraph(X[:n], oi, od, k)
+    same = 0
+    for j in range(100):
+        r = O.gnns(og, X[n + j], key=500 + j, k=k, restarts=R, seed=99, record=True)
+        if tr[j, :ev[j]].tolist() == r.sequence:
+            same += 1
+    say(f"  float GNNS identical evaluation order: {same}/100")
+    assert same >= 95

@@ -254,3 +254,12 @@ def test_errors_leave_graph_unchanged(G):
     assert g.n == 500
     after = [a.cpu().numpy() for a in g.lists()]
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+
+
+@pytest.mark.parametrize("depth", [5, 6])
+def test_deep_update_level_arrays_in_workspace(G, depth):
+    """Depths whose level arrays exceed LDS (k^(depth-1) slots) keep them in
+    the workspace; results stay bit-exact."""
+    X = u8_points(15, 1500 + 40, 16, clusters=3, sigma=14.0)
+    say(f"deep update depth={depth}")
+    _run_inserts(G, X, 1500, [24, 1, 15], 10, 8, depth=depth)

@@ -69,6 +69,13 @@ typedef enum {
 } knng_stage;
 typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } knng_score;
 
+/* Dissimilarity.  KNNG_METRIC_L2: squared Euclidean distance.
+ * KNNG_METRIC_COSINE (float data only): points are normalized to unit length
+ * when stored and when searched, and the dissimilarity is the squared
+ * distance of the normalized points, 2 (1 - cos), in [0, 4]; a zero vector
+ * stays zero.  The method applies to any dissimilarity (Section 3). */
+typedef enum { KNNG_METRIC_L2 = 0, KNNG_METRIC_COSINE = 1 } knng_metric;
+
 /*
  * Parameters (Section 3 and Algorithm 2 of the paper).
  *  dim        coordinates per point, 1 .. 4096.
@@ -89,6 +96,7 @@ typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } k
  *             k + k^2 + ... + k^depth <= 2^24 (the workspace holds that many
  *             proposal slots per batch point; k = 10 allows depth 7).
  *  seed       seed of the restart permutations (see knng_search).
+ *  metric     knng_metric (0 = squared L2).
  */
 typedef struct {
   int32_t  dim;
@@ -102,6 +110,7 @@ typedef struct {
   int32_t  expansion_den;
   int32_t  depth;
   uint64_t seed;
+  int32_t  metric;         /* knng_metric */
 } knng_params;
 
 /* Bytes of graph storage for params->capacity nodes (0 if params are
@@ -236,7 +245,8 @@ knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* 
 knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,
                            int32_t* ids_dev, void* d_dev, hipStream_t stream);
 
-/* Copy points [first, first + count) out as [count][dim] in the input dtype. */
+/* Copy points [first, first + count) out as [count][dim] in the input dtype
+ * (for the cosine metric: the stored, unit-length points). */
 knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count,
                             void* x_dev, hipStream_t stream);
 

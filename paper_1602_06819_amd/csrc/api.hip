@@ -181,6 +181,10 @@ knng_status check_params(const knng_params* p) {
     return fail(KNNG_EINVAL, "unknown score %d", p->score);
   if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
     return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
+  if (p->metric != KNNG_METRIC_L2 && p->metric != KNNG_METRIC_COSINE)
+    return fail(KNNG_EINVAL, "unknown metric %d", p->metric);
+  if (p->metric == KNNG_METRIC_COSINE && p->dtype != KNNG_F32)
+    return fail(KNNG_EINVAL, "the cosine metric needs float data");
   if (p->dtype == KNNG_U8 && p->dim > 256)
     return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
   if (p->dtype == KNNG_F32) {
@@ -217,6 +221,7 @@ StorageLayout storage_layout(const knng_params& p) {
   S.k_pad = k_pad_of(p.k);
   S.format = row_format(p);
   S.is_float = p.dtype == KNNG_F32;
+  S.cosine = p.metric == KNNG_METRIC_COSINE;
   S.pad = S.is_float ? (int32_t)0x7f800000 : DIST_PAD_I32;
   S.mstride = S.is_float ? (int)round_up(p.dim, 4) : 0;
   switch (S.format) {
@@ -271,6 +276,7 @@ WorkspaceLayout workspace_layout(const knng_params& p, const StorageLayout& S) {
     W.set_words_pad = set_bytes(S.cap) / 4;
     W.off_sets = take(cur, (size_t)W.set_slots * W.set_words_pad * 4);
   }
+  if (S.cosine) W.off_qbuf = take(cur, 2 * M * (size_t)S.dim * 4);
   if (S.is_float) {
     W.cand_rows = S.cap < CAND_ROWS ? S.cap : CAND_ROWS;
     W.off_cand = take(cur, (size_t)W.cand_rows * exact_km(p.k) * 8);
@@ -361,6 +367,26 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.dim = S.dim;
   a.rows[0] = r0;
   if (r1) a.rows[1] = *r1;
+  if (S.cosine) {
+    // the searches read their queries normalized, as the stored rows are
+    float* qbuf = at<float>(g->ws, W.off_qbuf);
+    int64_t at_row = 0;
+    for (int gi = 0; gi < 2; ++gi) {
+      SearchRows& R = a.rows[gi];
+      if (R.count <= 0) continue;
+      if (at_row + R.count > 2 * W.M)
+        return fail(KNNG_ECAPACITY, "cosine searches take at most max_batch queries per call");
+      IngestF32Args n{};
+      n.x = (const float*)R.qraw;
+      n.m = R.count;
+      n.dim = S.dim;
+      n.cosine = 1;
+      n.qout = qbuf + at_row * S.dim;
+      KNNG_TRY(launch_ingest_f32(n, stream), "normalize launch");
+      R.qraw = n.qout;
+      at_row += R.count;
+    }
+  }
   a.pad_bits = (uint32_t)S.pad;
   if (search_sets_global(g->n)) {
     a.gvis = at<uint32_t>(g->ws, W.off_sets);
@@ -441,6 +467,7 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipSt
     a.stride = S.mstride;
     a.row_bytes = S.row_bytes;
     a.format = S.format;
+    a.cosine = S.cosine ? 1 : 0;
     KNNG_TRY(launch_ingest_f32(a, stream), "ingest launch");
   }
   return KNNG_OK;

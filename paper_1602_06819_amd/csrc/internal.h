@@ -30,6 +30,7 @@ enum RowFormat { ROW_I8 = 0, ROW_BF16 = 1, ROW_FP8 = 2, ROW_F32 = 3 };
 struct StorageLayout {
   int dim = 0, k = 0, k_pad = 0, row_bytes = 0, format = ROW_I8, mstride = 0;
   bool is_float = false;
+  bool cosine = false; // rows normalized to unit length (cosine metric)
   int32_t pad = 0;     // distance padding pattern
   int64_t cap = 0;
   size_t off_vec = 0, off_scale = 0, off_master = 0, off_norms = 0, off_ids = 0, off_dist = 0,
@@ -48,6 +49,7 @@ struct StorageLayout {
 //                 block, for graphs whose bitset does not fit in LDS
 //   cand          float exact graph: candidate keys of a chunk of nodes
 //   fronts        update level arrays that do not fit in LDS, per block
+//   qbuf          cosine metric: the normalized rows of a search's queries
 struct WorkspaceLayout {
   int64_t M = 0;
   int64_t props_per_point = 0;
@@ -56,7 +58,7 @@ struct WorkspaceLayout {
   int64_t cand_rows = 0;
   size_t off_res_ids = 0, off_res_d = 0, off_evals = 0,
          off_upd = 0, off_lreads = 0, off_props = 0, off_touched = 0, off_counters = 0, off_partial = 0,
-         off_keys = 0, off_sets = 0, off_cand = 0, off_fronts = 0, total = 0;
+         off_keys = 0, off_sets = 0, off_cand = 0, off_fronts = 0, off_qbuf = 0, total = 0;
 };
 
 struct Proposal {
@@ -83,6 +85,8 @@ struct IngestF32Args {
   float* scale;        // [m] (FP8)
   int64_t m;
   int dim, stride, row_bytes, format;
+  int cosine;          // normalize rows to unit length first
+  float* qout;         // if set: write only the normalized rows [m][dim] here
 };
 
 struct ExactArgs {

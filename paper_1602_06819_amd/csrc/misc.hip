@@ -8,8 +8,9 @@
 // multiple of 16); padding contributes nothing to any distance.  The row's
 // squared norm (an int32: at most 4096 * 128^2) is stored beside it.
 //
-// Ingest of float32 points: the float32 row itself (zero padded to a
-// multiple of 4 coordinates: the rows of the stored float distances), its
+// Ingest of float32 points (normalized to unit length first for the cosine
+// metric): the float32 row itself (zero padded to a multiple of 4
+// coordinates: the rows of the stored float distances), its
 // squared norm (for the exact graph's expansion), and the scoring row of
 // the search: bfloat16 by round-to-nearest-even, or FP8 E4M3 codes
 // RNE(x / s) with one scale s = max |x| / 448 per row (s = 0 for a zero
@@ -51,16 +52,40 @@ hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One wave per row; lane j takes coordinates j, j + 64, ...
+// One wave per row; lane j takes coordinates j, j + 64, ...  Sums are taken
+// per lane in ascending coordinate order and then over lanes in an xor tree,
+// so a row's values depend on the row only.  With `cosine` the row is first
+// divided by its Euclidean norm (a zero row stays zero), and every stored
+// value derives from the normalized row; with `qout` only the normalized
+// row is written, [m][dim], for the queries of a search.
+__device__ __forceinline__ float wave_sum_sq(const float* src, int dim, int lane) {
+  float s = 0.f;
+  for (int j = lane; j < dim; j += WAVE) s = __builtin_fmaf(src[j], src[j], s);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, WAVE);
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_ingest_f32(IngestF32Args a) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= a.m) return;
+  if (row >= a.m) return;                          // uniform per wavefront
   const float* src = a.x + row * a.dim;
+  float div = 1.f;
+  if (a.cosine) {
+    const float len = __builtin_sqrtf(wave_sum_sq(src, a.dim, lane));
+    div = len > 0.f ? len : 1.f;
+  }
+  auto value = [&](int j) { return a.cosine ? src[j] / div : src[j]; };
+  if (a.qout) {
+    float* qrow = a.qout + row * a.dim;
+    for (int j = lane; j < a.dim; j += WAVE) qrow[j] = value(j);
+    return;
+  }
   float* mrow = a.master + row * a.stride;
   float nrm = 0.f, mx = 0.f;
   for (int j = lane; j < a.stride; j += WAVE) {
-    const float v = j < a.dim ? src[j] : 0.f;
+    const float v = j < a.dim ? value(j) : 0.f;
     mrow[j] = v;
     nrm = __builtin_fmaf(v, v, nrm);
     mx = fmaxf(mx, fabsf(v));
@@ -74,12 +99,12 @@ __global__ __launch_bounds__(256) void k_ingest_f32(IngestF32Args a) {
   if (a.format == ROW_BF16) {
     uint16_t* brow = reinterpret_cast<uint16_t*>(a.score + row * a.row_bytes);
     for (int j = lane; j < a.row_bytes / 2; j += WAVE)
-      brow[j] = (uint16_t)(j < a.dim ? f32_to_bf16(src[j]) : 0u);
+      brow[j] = (uint16_t)(j < a.dim ? f32_to_bf16(value(j)) : 0u);
   } else if (a.format == ROW_FP8) {
     const float scale = mx / 448.f;
     uint8_t* frow = reinterpret_cast<uint8_t*>(a.score + row * a.row_bytes);
     for (int j = lane; j < a.row_bytes; j += WAVE)
-      frow[j] = (uint8_t)((j < a.dim && scale > 0.f) ? f32_to_e4m3(src[j] / scale) : 0u);
+      frow[j] = (uint8_t)((j < a.dim && scale > 0.f) ? f32_to_e4m3(value(j) / scale) : 0u);
     if (lane == 0) a.scale[row] = scale;
   }
 }

@@ -17,6 +17,7 @@ from ._lib import check, knng_params
 _DTYPES = {"u8": _lib.KNNG_U8, "f32": _lib.KNNG_F32}
 _SCORES = {"exact": _lib.KNNG_SCORE_EXACT, "bf16": _lib.KNNG_SCORE_BF16,
            "fp8": _lib.KNNG_SCORE_FP8}
+_METRICS = {"l2": _lib.KNNG_METRIC_L2, "cosine": _lib.KNNG_METRIC_COSINE}
 
 
 @dataclass(frozen=True)
@@ -32,13 +33,14 @@ class GraphConfig:
     seed: int = 0x5EED
     dtype: str = "u8"
     score: str = "exact"
+    metric: str = "l2"
 
     def params(self) -> knng_params:
         return knng_params(dim=self.dim, k=self.k, dtype=_DTYPES[self.dtype],
                            score=_SCORES[self.score], capacity=self.capacity,
                            max_batch=self.max_batch, speedup=self.speedup,
                            expansion_num=self.expansion_num, expansion_den=self.expansion_den,
-                           depth=self.depth, seed=self.seed)
+                           depth=self.depth, seed=self.seed, metric=_METRICS[self.metric])
 
 
 def storage_bytes(cfg: GraphConfig) -> int:

@@ -40,8 +40,9 @@ def test_library_exports_every_declared_function(L):
 
 
 def test_params_struct_size_matches_header(L):
-    # int32 x4, int64 x2, int32 x4, uint64 -> 56 bytes, natural alignment
-    assert ctypes.sizeof(L.knng_params) == 56
+    # int32 x4, int64 x2, int32 x4, uint64, int32 (+ 4 padding) -> 64 bytes
+    assert ctypes.sizeof(L.knng_params) == 64
+    assert L.knng_params.metric.offset == 56
 
 
 def _p(L, **kw):
@@ -55,12 +56,22 @@ def _p(L, **kw):
                                  dict(expansion_num=1, expansion_den=1), dict(depth=9), dict(depth=0),
                                  dict(k=64, depth=4),
                                  dict(capacity=1), dict(max_batch=0), dict(max_batch=2000),
-                                 dict(score=1), dict(dim=300)])
+                                 dict(score=1), dict(dim=300), dict(metric=2), dict(metric=1),
+                                 dict(dtype=1, score=0, dim=300), dict(dtype=1, score=1, dim=600),
+                                 dict(dtype=1, score=2, dim=1100)])
 def test_invalid_params_are_rejected(L, bad):
     p = _p(L, **bad)
     assert L.lib.knng_storage_bytes(ctypes.byref(p)) == 0
     assert L.lib.knng_workspace_bytes(ctypes.byref(p)) == 0
     assert L.last_error() != ""
+
+
+def test_valid_float_shapes_and_cosine_are_accepted(L):
+    for kw in (dict(dtype=1, score=2, dim=960, k=50), dict(dtype=1, score=1, dim=512),
+               dict(dtype=1, score=0, dim=256, metric=1), dict(depth=5), dict(depth=7)):
+        p = _p(L, **kw)
+        assert L.lib.knng_storage_bytes(ctypes.byref(p)) > 0, (kw, L.last_error())
+        assert L.lib.knng_workspace_bytes(ctypes.byref(p)) > 0
 
 
 def test_sizes_grow_with_capacity_and_batch(L):

@@ -25,6 +25,9 @@ silent are listed in each function's docstring):
 * read-only k-nn query on the current graph   -> :func:`online.query`
 * GNNS, the baseline iGNNS improves on (fixed number of restarts, steepest
   climb over every neighbour)                 -> :func:`gnns.gnns`
+* balanced k-medoids partitioning (Algorithm 4, one compute node) and the
+  search of every partition merged to the k best (Algorithm 3)
+                                              -> :mod:`partition`
 * cosine dissimilarity 2 (1 - cos) as squared distance of normalized
   points                                      -> :mod:`cosine`
 * the number formats of the float path's scoring rows (bfloat16, FP8 E4M3
@@ -47,6 +50,6 @@ from .exact import ExactRows, exact_graph, exact_graph_loops, exact_row  # noqa:
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
 from .gnns import gnns  # noqa: F401
-from . import cosine, quantize  # noqa: F401
+from . import cosine, partition, quantize  # noqa: F401
 from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401
                      BatchResult, QUERY_KEY_BASE)

@@ -36,9 +36,22 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import numpy as np
+
 from .distance import sqdist
 from .graph import OracleGraph, Params, budget
 from .restart import RestartOrder
+
+
+class _Excluding(set):
+    """A visited set that also contains every node outside ``allowed``."""
+
+    def __init__(self, base, allowed):
+        super().__init__(base)
+        self.allowed = allowed
+
+    def __contains__(self, v):
+        return (not self.allowed[v]) or set.__contains__(self, v)
 
 
 @dataclass
@@ -54,16 +67,25 @@ def expansion_rejects(d_r, d_best, e_num: int, e_den: int) -> bool:
 
 
 def ignns(g: OracleGraph, q, key: int, p: Params, n: int | None = None,
-          record: bool = False) -> SearchResult:
+          record: bool = False, allowed=None) -> SearchResult:
     """Search the k nearest neighbours of point q among nodes [0, n) of g.
 
     ``n`` defaults to the whole graph; the adjacency lists used are g's
-    lists of those nodes (the snapshot).
+    lists of those nodes (the snapshot).  ``allowed`` (a boolean array over
+    the nodes, or None) restricts the search to a subgraph: nodes outside it
+    are never drawn, evaluated or counted, as if they were not in the graph,
+    and the budget is that of the subgraph's size (the search of one
+    partition in Algorithm 3).
     """
     n = g.n if n is None else n
-    B = budget(n, p.k, p.speedup)
+    size = n if allowed is None else int(np.count_nonzero(allowed[:n]))
+    B = budget(size, p.k, p.speedup)
     order = RestartOrder(n, p.seed, key)
     visited: set[int] = set()
+    if allowed is not None:
+        # nodes outside the subgraph behave as already visited: skipped by
+        # the restart draw and by the climb, never evaluated
+        visited = _Excluding(visited, allowed)
     evaluated: list[tuple] = []
     seq: list[int] | None = [] if record else None
     state = {"evals": 0, "best": None}

@@ -1,0 +1,116 @@
+"""Partitioned search on one device: balanced k-medoids partitioning
+(Algorithm 4) and the search of every partition merged to the k best
+(Algorithm 3), as test infrastructure for the GPU's partitioned search.
+
+Readings, where the paper leaves points open:
+
+* One compute node (c = 1): capacity = n * imbalance / p, imbalance given
+  as a fraction num / den >= 1.
+* Initial medoids: the first p distinct nodes of the keyed restart
+  permutation with key 2^61 (the same generator as the search's restarts).
+* Assign: nodes are taken in id order; node u joins the medoid m that
+  maximizes similarity(u, m) * w(m) with similarity 1 / (1 + d) and
+  w(m) = 1 - |C(m)| / capacity, |C(m)| the cluster's size at that moment.
+  In exact arithmetic: m beats m' iff
+      (N - |C(m)| P) (1 + d(u, m')) > (N - |C(m')| P) (1 + d(u, m)),
+  N = n num, P = p den; ties go to the smaller medoid index.
+* Update: the new medoid of a cluster is its member with the smallest sum
+  of dissimilarities to the cluster's members (ties: smaller id); the
+  paper's graph shortest paths are replaced by the dissimilarity itself,
+  the heuristic it already uses for the assign step.  An empty cluster
+  keeps its medoid.
+* Iterations: a fixed number; each is an assign then an update; the
+  partition is the last assignment.
+* Search of a partition: iGNNS restricted to the partition's nodes (the
+  induced subgraph), with the partition's own budget, and the query's key;
+  the result is the k best of the p partial results by (distance, id).
+"""
+
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+from .distance import sqdist, sqdist_many
+from .graph import OracleGraph, Params
+from .ignns import SearchResult, ignns
+from .restart import RestartOrder
+
+MEDOID_KEY = 1 << 61
+
+
+def initial_medoids(n: int, p: int, seed: int) -> list[int]:
+    order = RestartOrder(n, seed, MEDOID_KEY)
+    out: list[int] = []
+    while len(out) < p:
+        v = order.next_unvisited(set(out))
+        if v is None:
+            break
+        out.append(v)
+    return out
+
+
+def _better(wa: int, da, wb: int, db) -> bool:
+    """w_a / (1 + d_a) > w_b / (1 + d_b), exactly."""
+    if isinstance(da, int) and isinstance(db, int):
+        return wa * (1 + db) > wb * (1 + da)
+    return Fraction(wa) * (1 + Fraction(db)) > Fraction(wb) * (1 + Fraction(da))
+
+
+def assign(X: np.ndarray, medoids: list[int], imb_num: int, imb_den: int) -> np.ndarray:
+    n, p = X.shape[0], len(medoids)
+    N, P = n * imb_num, p * imb_den
+    size = [0] * p
+    part = np.empty(n, dtype=np.int64)
+    for u in range(n):
+        best = None
+        for m in range(p):
+            d = sqdist(X[u], X[medoids[m]])
+            w = N - size[m] * P
+            if best is None or _better(w, d, best[1], best[2]):
+                best = (m, w, d)
+        part[u] = best[0]
+        size[best[0]] += 1
+    return part
+
+
+def update(X: np.ndarray, part: np.ndarray, medoids: list[int]) -> list[int]:
+    out = list(medoids)
+    for m in range(len(medoids)):
+        members = np.nonzero(part == m)[0]
+        if len(members) == 0:
+            continue
+        best = None
+        for u in members:
+            s = sqdist_many(X[u], X[members])
+            tot = int(np.sum(s)) if X.dtype == np.uint8 else float(np.sum(s))
+            if best is None or (tot, int(u)) < best:
+                best = (tot, int(u))
+        out[m] = best[1]
+    return out
+
+
+def balanced_kmedoids(X: np.ndarray, p: int, iters: int, seed: int, imb_num: int = 1,
+                      imb_den: int = 1, medoids: list[int] | None = None):
+    """Returns (part [n], medoids [p])."""
+    meds = initial_medoids(X.shape[0], p, seed) if medoids is None else list(medoids)
+    part = None
+    for _ in range(iters):
+        part = assign(X, meds, imb_num, imb_den)
+        meds = update(X, part, meds)
+    return part, meds
+
+
+def partitioned_search(g: OracleGraph, part: np.ndarray, p: int, q, key: int,
+                       params: Params) -> tuple[SearchResult, list[int]]:
+    """Algorithm 3 on one device: every partition searched with iGNNS on its
+    own nodes, the k best of the union kept.  Returns the merged result and
+    the evaluations per partition."""
+    pairs, evals = [], []
+    for t in range(p):
+        r = ignns(g, q, key, params, allowed=(part == t))
+        pairs.extend(r.pairs)
+        evals.append(r.evals)
+    pairs.sort()
+    return SearchResult(pairs=pairs[:params.k], evals=sum(evals), sequence=None), evals

@@ -240,6 +240,45 @@ knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* 
                        int64_t m, int32_t* q_ids_dev, void* q_d_dev, int32_t* q_evals_dev,
                        int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream);
 
+/*
+ * Balanced k-medoids partitioning of the current graph's nodes into p
+ * parts (Algorithm 4 on one compute node; Section 6).  capacity =
+ * n * imb_num / (p * imb_den).  Initial medoids: the first p distinct ids of
+ * the restart permutation keyed 2^61 (seed `seed`).  Each of `iters`
+ * iterations assigns the nodes in id order, each to the medoid maximizing
+ * similarity * (1 - size / capacity) with similarity 1 / (1 + d) (exact
+ * comparisons; ties to the smaller medoid index), then makes each part's
+ * member with the smallest sum of dissimilarities to its part the new
+ * medoid (ties: smaller id).
+ *  p              1 .. 64, at most n.   imb_num / imb_den in [1, 64].
+ *  scratch_dev    device scratch of knng_partition_scratch_bytes(g, p)
+ *                 bytes, 256-byte aligned (owned by the caller).
+ *  part_dev       [n] int32 out: the part of every node (last assignment).
+ *  medoids_dev    [p] int32 out: the medoids after the last update.
+ */
+size_t knng_partition_scratch_bytes(const knng_graph* g, int32_t p);
+knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_num,
+                           int32_t imb_den, uint64_t seed, void* scratch_dev,
+                           size_t scratch_bytes, int32_t* part_dev, int32_t* medoids_dev,
+                           hipStream_t stream);
+
+/*
+ * Partitioned search (Algorithm 3 on one device): each query is searched
+ * with iGNNS in every part separately -- within a part, nodes of other parts
+ * are never drawn, evaluated or counted, and the budget is B(n_t) of the
+ * part's size -- and the k best of the p partial results are returned.  All
+ * m * p searches run in one launch.  uint8 graphs.
+ *  part_dev      [n] int32 part of each node (0 .. p-1), e.g. from
+ *                knng_partition.
+ *  scratch_dev   knng_search_partitioned_scratch_bytes(g, m, p) bytes.
+ *  ids_dev, d_dev [m][k] out; evals_dev [m] out (sum over the parts) or NULL.
+ */
+size_t knng_search_partitioned_scratch_bytes(const knng_graph* g, int64_t m, int32_t p);
+knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
+                                    const uint64_t* keys_dev, const int32_t* part_dev, int32_t p,
+                                    void* scratch_dev, size_t scratch_bytes, int32_t* ids_dev,
+                                    void* d_dev, int32_t* evals_dev, hipStream_t stream);
+
 /* Copy lists of nodes [first, first + count) out: ids_dev [count][k] int32,
  * d_dev [count][k] int32/float (either may be NULL). */
 knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,

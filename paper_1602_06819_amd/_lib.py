@@ -26,7 +26,8 @@ EXPORTED = [
     "knng_search", "knng_insert_batch", "knng_query", "knng_get_lists", "knng_get_points",
     "knng_size", "knng_query_count", "knng_last_error", "knng_destroy",
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
-    "knng_epoch", "knng_search_gnns",
+    "knng_epoch", "knng_search_gnns", "knng_partition_scratch_bytes", "knng_partition",
+    "knng_search_partitioned_scratch_bytes", "knng_search_partitioned",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -104,6 +105,17 @@ def _load() -> ctypes.CDLL:
     lib.knng_epoch.restype = ctypes.c_int
     lib.knng_search_gnns.argtypes = [vp, vp, i64, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     lib.knng_search_gnns.restype = ctypes.c_int
+    lib.knng_partition_scratch_bytes.argtypes = [vp, ctypes.c_int32]
+    lib.knng_partition_scratch_bytes.restype = ctypes.c_size_t
+    lib.knng_partition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp,
+                                   vp]
+    lib.knng_partition.restype = ctypes.c_int
+    lib.knng_search_partitioned_scratch_bytes.argtypes = [vp, i64, ctypes.c_int32]
+    lib.knng_search_partitioned_scratch_bytes.restype = ctypes.c_size_t
+    lib.knng_search_partitioned.argtypes = [vp, vp, i64, vp, vp, ctypes.c_int32, vp,
+                                            ctypes.c_size_t, vp, vp, vp, vp]
+    lib.knng_search_partitioned.restype = ctypes.c_int
     return lib
 
 

@@ -645,6 +645,72 @@ knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int
 }
 
 
+// ---- partitioning (host side) ------------------------------------------------
+// Host copy of the restart generator (the same SplitMix64 / LCG the search
+// kernel uses): the initial medoids are the first p distinct node ids of
+// the keyed permutation with key 2^61.
+uint64_t host_splitmix(uint64_t& s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void initial_medoids(int64_t n, int p, uint64_t seed, int32_t* out) {
+  const uint32_t m = modulus_for(n);
+  uint64_t s0 = (uint64_t)1 << 61;
+  const uint64_t hk = host_splitmix(s0);
+  uint64_t t = seed ^ hk;
+  const uint64_t r0 = host_splitmix(t), r1 = host_splitmix(t), r2 = host_splitmix(t);
+  uint32_t a = 1, c = 1;
+  if (m > 2) {
+    a = (uint32_t)(4ull * (r0 & (uint64_t)(m / 4 - 1)) + 1ull);
+    c = (uint32_t)(2ull * (r1 & (uint64_t)(m / 2 - 1)) + 1ull);
+  }
+  uint32_t x = (uint32_t)(r2 & (uint64_t)(m - 1));
+  int got = 0;
+  for (uint64_t step = 0; step < m && got < p; ++step) {
+    if ((int64_t)x < n) {
+      bool dup = false;
+      for (int i = 0; i < got; ++i) dup = dup || out[i] == (int32_t)x;
+      if (!dup) out[got++] = (int32_t)x;
+    }
+    x = (uint32_t)(((uint64_t)a * x + c) & (uint64_t)(m - 1));
+  }
+}
+
+struct PartScratch {
+  size_t off_D = 0, off_members = 0, off_offsets = 0, off_sums = 0, total = 0;
+};
+
+PartScratch part_scratch(int64_t n, int p) {
+  PartScratch P;
+  size_t cur = 0;
+  P.off_D = take(cur, (size_t)n * p * 4);
+  P.off_members = take(cur, (size_t)n * 4);
+  P.off_offsets = take(cur, 65 * 4);
+  P.off_sums = take(cur, (size_t)n * 8);
+  P.total = cur;
+  return P;
+}
+
+struct SearchPartScratch {
+  size_t off_ids = 0, off_d = 0, off_evals = 0, off_counts = 0, off_budgets = 0, total = 0;
+};
+
+SearchPartScratch search_part_scratch(int64_t m, int p, int k_pad) {
+  SearchPartScratch P;
+  size_t cur = 0;
+  P.off_ids = take(cur, (size_t)m * p * k_pad * 4);
+  P.off_d = take(cur, (size_t)m * p * k_pad * 4);
+  P.off_evals = take(cur, (size_t)m * p * 4);
+  P.off_counts = take(cur, 64 * 4);
+  P.off_budgets = take(cur, 64 * 4);
+  P.total = cur;
+  return P;
+}
+
 }  // namespace
 
 extern "C" {
@@ -904,6 +970,128 @@ knng_status knng_get_rows(const knng_graph* g, int64_t first, int64_t count, voi
     KNNG_TRY(hipMemcpyAsync(scale_dev, at<float>(g->st, S.off_scale) + first,
                             (size_t)count * 4, hipMemcpyDeviceToDevice, stream),
              "copy scales");
+  return ok();
+}
+
+
+size_t knng_partition_scratch_bytes(const knng_graph* g, int32_t p) {
+  if (!g || p < 1 || p > 64) return 0;
+  return part_scratch(g->n, p).total;
+}
+
+knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_num,
+                           int32_t imb_den, uint64_t seed, void* scratch_dev,
+                           size_t scratch_bytes, int32_t* part_dev, int32_t* medoids_dev,
+                           hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
+  if (p > g->n) return fail(KNNG_EINVAL, "p exceeds the number of nodes");
+  if (iters < 1) return fail(KNNG_EINVAL, "iters must be >= 1");
+  if (imb_den < 1 || imb_num < imb_den || imb_num > 64 * imb_den)
+    return fail(KNNG_EINVAL, "imbalance num/den must be in [1, 64] with den >= 1");
+  knng_status s;
+  if ((s = check_ptr(scratch_dev, "scratch_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(part_dev, "part_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(medoids_dev, "medoids_dev")) != KNNG_OK) return s;
+  if ((uintptr_t)scratch_dev % ALIGN) return fail(KNNG_EINVAL, "scratch must be 256-byte aligned");
+  const PartScratch P = part_scratch(g->n, p);
+  if (scratch_bytes < P.total)
+    return fail(KNNG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, P.total);
+  const StorageLayout& S = g->S;
+  char* sc = (char*)scratch_dev;
+  PartitionArgs a{};
+  a.format = S.is_float ? ROW_F32 : ROW_I8;
+  a.vec = S.is_float ? (const void*)at<char>(g->st, S.off_master)
+                     : (const void*)at<char>(g->st, S.off_vec);
+  a.row_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
+  a.dim = S.dim;
+  a.n = (int32_t)g->n;
+  a.p = p;
+  a.N = g->n * (int64_t)imb_num;
+  a.P = (int64_t)p * imb_den;
+  a.medoids = medoids_dev;
+  a.D = reinterpret_cast<uint32_t*>(sc + P.off_D);
+  a.part = part_dev;
+  a.members = reinterpret_cast<int32_t*>(sc + P.off_members);
+  a.offsets = reinterpret_cast<int32_t*>(sc + P.off_offsets);
+  a.sums = reinterpret_cast<double*>(sc + P.off_sums);
+  a.is_float = S.is_float ? 1 : 0;
+  int32_t init[64];
+  initial_medoids(g->n, p, seed, init);
+  KNNG_TRY(launch_set_medoids(medoids_dev, init, p, stream), "medoids launch");
+  for (int it = 0; it < iters; ++it)
+    KNNG_TRY(launch_partition_iteration(a, stream), "partition launch");
+  return ok();
+}
+
+size_t knng_search_partitioned_scratch_bytes(const knng_graph* g, int64_t m, int32_t p) {
+  if (!g || m < 0 || p < 1 || p > 64) return 0;
+  return search_part_scratch(m, p, g->S.k_pad).total;
+}
+
+knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
+                                    const uint64_t* keys_dev, const int32_t* part_dev, int32_t p,
+                                    void* scratch_dev, size_t scratch_bytes, int32_t* ids_dev,
+                                    void* d_dev, int32_t* evals_dev, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (m == 0) return ok();
+  if (m < 0 || m * (int64_t)p >= ((int64_t)1 << 31))
+    return fail(KNNG_EINVAL, "m * p must be below 2^31");
+  if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
+  if (g->S.is_float) return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs");
+  knng_status s;
+  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(part_dev, "part_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(scratch_dev, "scratch_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  if ((uintptr_t)scratch_dev % ALIGN) return fail(KNNG_EINVAL, "scratch must be 256-byte aligned");
+  const SearchPartScratch P = search_part_scratch(m, p, g->S.k_pad);
+  if (scratch_bytes < P.total)
+    return fail(KNNG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, P.total);
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  char* sc = (char*)scratch_dev;
+  int32_t* rid = reinterpret_cast<int32_t*>(sc + P.off_ids);
+  int32_t* rd = reinterpret_cast<int32_t*>(sc + P.off_d);
+  int32_t* rev = reinterpret_cast<int32_t*>(sc + P.off_evals);
+  int32_t* counts = reinterpret_cast<int32_t*>(sc + P.off_counts);
+  int32_t* budgets = reinterpret_cast<int32_t*>(sc + P.off_budgets);
+  KNNG_TRY(launch_part_budgets(part_dev, (int32_t)g->n, p, S.k, g->p.speedup, counts, budgets,
+                               stream),
+           "budget launch");
+  SearchArgs a{};
+  a.format = S.format;
+  a.vec = at<char>(g->st, S.off_vec);
+  a.row_bytes = S.row_bytes;
+  a.nbr_ids = at<int32_t>(g->st, S.off_ids);
+  a.k = S.k;
+  a.k_pad = S.k_pad;
+  a.keep = S.k;
+  a.n = (int32_t)g->n;
+  a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
+  a.m_mod = modulus_for(g->n);
+  a.e_num = g->p.expansion_num;
+  a.e_den = g->p.expansion_den;
+  a.seed = g->p.seed;
+  a.dim = S.dim;
+  a.rows[0] = query_rows(q_dev, m * p, keys_dev, 0, rid, rd, S.k_pad, rev, nullptr, nullptr, 0);
+  a.pad_bits = (uint32_t)S.pad;
+  if (search_sets_global(g->n)) {
+    a.gvis = at<uint32_t>(g->ws, W.off_sets);
+    a.gvis_slots = W.set_slots;
+  }
+  a.node_part = part_dev;
+  a.nparts = p;
+  a.part_budget = budgets;
+  {
+    Timed t(g, KNNG_STAGE_QUERY, stream);
+    KNNG_TRY(launch_search_part(a, stream), "search launch");
+    KNNG_TRY(launch_merge_partitions(rid, rd, rev, S.k_pad, (int32_t)m, p, S.k, ids_dev,
+                                     (int32_t*)d_dev, S.k, evals_dev, S.pad, stream),
+             "merge launch");
+  }
   return ok();
 }
 

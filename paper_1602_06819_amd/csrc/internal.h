@@ -142,6 +142,25 @@ struct SearchArgs {
   uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
   int32_t vis_words, vis_words_pad;    // set by the launcher from n
   int32_t restarts;      // GNNS mode: number of restarts (launch_search_gnns)
+  // partitioned search (launch_search_part): node -> partition, partitions,
+  // and the budget of each partition
+  const int32_t* node_part; int32_t nparts; const int32_t* part_budget;
+};
+
+// Balanced k-medoids (partition.hip).  Rows of the distance evaluations as
+// in UpdateArgs (int8 rows or float32 rows).
+struct PartitionArgs {
+  int format;
+  const void* vec; int row_bytes; int dim;
+  int32_t n, p;
+  int64_t N, P;                 // capacity weight: w(m) = N - |C(m)| P
+  int32_t* medoids;             // [p]
+  uint32_t* D;                  // [n][p] distance bits node -> medoid
+  int32_t* part;                // [n]
+  int32_t* members;             // [n] node ids grouped by partition, ascending
+  int32_t* offsets;             // [p + 1]
+  double* sums;                 // [n] sum of distances to the own partition
+  int is_float;
 };
 
 struct PeerArgs {
@@ -198,6 +217,15 @@ hipError_t launch_split_merge(const uint64_t* partial, int32_t nq, int32_t nspli
                               int32_t* out_ids, int32_t* out_d, int out_stride, hipStream_t s);
 hipError_t launch_search(const SearchArgs& a, hipStream_t s);
 hipError_t launch_search_gnns(const SearchArgs& a, hipStream_t s);
+hipError_t launch_search_part(const SearchArgs& a, hipStream_t s);
+hipError_t launch_partition_iteration(const PartitionArgs& a, hipStream_t s);
+hipError_t launch_set_medoids(int32_t* medoids, const int32_t* host_ids, int p, hipStream_t s);
+hipError_t launch_part_budgets(const int32_t* part, int32_t n, int32_t p, int k, int speedup,
+                               int32_t* counts, int32_t* budgets, hipStream_t s);
+hipError_t launch_merge_partitions(const int32_t* ids, const int32_t* d, const int32_t* evals,
+                                   int stride, int32_t m, int32_t p, int k, int32_t* out_ids,
+                                   int32_t* out_d, int out_stride, int32_t* out_evals,
+                                   int32_t pad, hipStream_t s);
 hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);

@@ -216,8 +216,13 @@ struct ScoreF32 {
 // and moves to the closest of them if it is strictly closer than the
 // current node, and the search ends after a.restarts restarts and their
 // climbs (or at the budget).
+//
+// PART (partitioned search on one device): row r of a group searches query
+// r / nparts within partition r % nparts only -- nodes of other partitions
+// are never evaluated or counted, as if absent -- with that partition's
+// budget; the rows' results are merged afterwards (k_merge_partitions).
 template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB,
-          bool GNNS = false>
+          bool GNNS = false, bool PART = false>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[WAVE], tk_o[WAVE];
@@ -240,7 +245,10 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     // the row's group and index in it (uniform across the wavefront)
     const bool g0 = qg < a.rows[0].count;
     const SearchRows& R = g0 ? a.rows[0] : a.rows[1];
-    const int32_t qi = g0 ? qg : qg - a.rows[0].count;
+    const int32_t qi = g0 ? qg : qg - a.rows[0].count;      // output row
+    const int32_t part = PART ? qi % a.nparts : 0;          // partition searched
+    const int32_t qq = PART ? qi / a.nparts : qi;           // query of the row
+    const int32_t Bq = PART ? a.part_budget[part] : a.B;    // the row's budget
     uint32_t* vis = GVIS ? a.gvis + (int64_t)blockIdx.x * a.vis_words_pad : lds;
     if (GVIS) {
       for (int w = lane * 4; w < a.vis_words_pad; w += WAVE * 4)
@@ -252,8 +260,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     __syncthreads();
 
     Score sc;
-    sc.load(a, R, qi);
-    const uint64_t key = R.keys ? R.keys[qi] : R.key_base + (uint64_t)qi;
+    sc.load(a, R, qq);
+    const uint64_t key = R.keys ? R.keys[qq] : R.key_base + (uint64_t)qq;
     const Lcg lcg = restart_lcg(a.seed, key, a.m_mod);
 
     // lane j holds the map x -> A x + C of j LCG steps (lane 0: identity)
@@ -295,6 +303,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     int32_t cidL = -1;              // lane view
     uint32_t xL = 0;
     int32_t cidG[G];                // group view
+    int32_t pg[G];                  // PART: partitions of the group-view candidates
+    int32_t partL = -1;             // PART: partition of the lane-view candidate
     v4i xv[NB][PB][CPL];            // gathered rows, by buffer and pass in group
     v4i lv[NB][PB][LCPL];           // gathered adjacency rows
     uint32_t sv[NB][PB];            // per-row side value (FP8 scale)
@@ -324,6 +334,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             xv[buf][q][pp] = v4i{0, 0, 0, 0};
         }
         if (Score::kSide) sv[buf][q] = ok ? a.side[cidG[p]] : 0u;
+        if (PART) pg[p] = ok ? a.node_part[cidG[p]] : -1;
         if (LISTS) {
 #pragma unroll
           for (int lc = 0; lc < LCPL; ++lc) {
@@ -335,7 +346,10 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         }
       }
     };
-    auto issue = [&]() { issue_group(0, 0); };
+    auto issue = [&]() {
+      if (PART) partL = cidL >= 0 ? a.node_part[cidL] : -1;
+      issue_group(0, 0);
+    };
 
     // A list scan whose k candidates fit one pass is decided in the group
     // view itself ("spaced": candidate c owned by lane c * G), without
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     const bool climb_spaced = G > 1 && (a.k + SLOTS - 1) / SLOTS == 1;
 
     int restarts_used = 0;          // GNNS: restarts taken
-    bool done = a.B <= 0 || (GNNS && a.restarts <= 0);
+    bool done = Bq <= 0 || (GNNS && a.restarts <= 0);
     if (!done) {
       window();
       issue();
@@ -410,7 +424,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 #pragma unroll
         for (int p = 0; p < G; ++p) to_lane(p);
       }
-      const bool valid = owner && cand >= 0 && !seen;
+      const bool inpart = !PART || (spaced ? pg[0] : partL) == part;
+      const bool valid = owner && cand >= 0 && !seen && inpart;
 
       // the sequential rule on this step's candidates
       const uint64_t V = ballot(valid);
@@ -435,7 +450,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       }
       const int f = S ? __ffsll((long long)S) - 1 : WAVE;
       uint64_t C = (GNNS && climbing) ? V : (f < WAVE ? (V & ((2ull << f) - 1ull)) : V);
-      const int rem = a.B - evals;
+      const int rem = Bq - evals;
       bool stop = false;
       if (__popcll(C) >= rem) {
         const bool in = ((C >> lane) & 1ull) && rank_below(C) < rem;
@@ -514,7 +529,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 
     if constexpr (CCPL > 0) {
       float qc[CCPL][4];
-      canon_load_query<CCPL>((const float*)R.qraw + (int64_t)qi * a.dim, a.dim, qc);
+      canon_load_query<CCPL>((const float*)R.qraw + (int64_t)qq * a.dim, a.dim, qc);
       const bool have = lane < kk && rk != KEY_INF;
       const int32_t cid = have ? key_id(rk) : -1;
       const uint32_t d32 =
@@ -540,11 +555,12 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 // Launch of one instantiation; LROW from the list stride (adjacency rows
 // of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
 // `vis_lds` is the LDS of the visited set (0 when it is global).
-template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false>
+template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false,
+          bool PART = false>
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
   const bool gvis = a.gvis != nullptr;
-#define KNNG_SEARCH_GO(LR, GV)                                                              \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS>), dim3(grid),   \
+#define KNNG_SEARCH_GO(LR, GV)                                                                 \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART>), dim3(grid), \
                      dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.k_pad == 16) {
     if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);

@@ -53,6 +53,30 @@ hipError_t launch_search_gnns(const SearchArgs& a0, hipStream_t s) {
   return launch_search_i8_gnns(a, s, (unsigned)grid, lds);
 }
 
+// Partitioned search on int8 rows: rows are (query, partition) pairs.
+hipError_t launch_search_part(const SearchArgs& a0, hipStream_t s) {
+  SearchArgs a = a0;
+  a.m = a.rows[0].count + a.rows[1].count;
+  if (a.m <= 0) return hipSuccess;
+  if (a.format != ROW_I8 || a.nparts < 1 || !a.node_part || !a.part_budget)
+    return hipErrorInvalidValue;
+  a.vis_words = (int32_t)((a.n + 31) / 32);
+  a.vis_words_pad = (int32_t)round_up(a.vis_words, 4);
+  const bool gvis = a.gvis != nullptr;
+  const size_t lds = search_lds_bytes(a.n, a.k_pad, gvis);
+  int64_t grid = a.m < 1048576 ? a.m : 1048576;
+  if (gvis && grid > a.gvis_slots) grid = a.gvis_slots;
+  if (grid < 1) return hipErrorInvalidValue;
+  const unsigned gr = (unsigned)grid;
+  const int chunks = a.row_bytes / 16;
+  if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1, 1, false, true>(a, s, gr, lds);
+  if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1, 2, false, true>(a, s, gr, lds);
+  if (chunks <= 4) return launch_search_t<ScoreI8<4, 1>, 4, 1, 0, 1, 4, false, true>(a, s, gr, lds);
+  if (chunks <= 8) return launch_search_t<ScoreI8<4, 2>, 4, 2, 0, 1, 4, false, true>(a, s, gr, lds);
+  if (chunks <= 16) return launch_search_t<ScoreI8<4, 4>, 4, 4, 0, 1, 4, false, true>(a, s, gr, lds);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_search(const SearchArgs& a0, hipStream_t s) {
   SearchArgs a = a0;
   a.m = a.rows[0].count + a.rows[1].count;

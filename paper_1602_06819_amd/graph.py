@@ -232,6 +232,40 @@ class KnnGraph:
                                         _ptr(d), _ptr(ev), _ptr(tr), stride, _stream(stream)))
         return ids, d, ev, tr
 
+    def partition(self, p: int, iters: int = 5, imbalance=(1, 1), seed: int = 0x5EED,
+                  stream=None):
+        """Balanced k-medoids parts of the current nodes; returns (part [n],
+        medoids [p]) as int32 device tensors."""
+        nbytes = _lib.lib.knng_partition_scratch_bytes(self._h, p)
+        if nbytes == 0:
+            raise _lib.KnngError(_lib.KNNG_EINVAL, "invalid number of parts")
+        scratch = _aligned_buffer(nbytes, self.device)
+        part = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        med = torch.empty(p, dtype=torch.int32, device=self.device)
+        check(_lib.lib.knng_partition(self._h, p, iters, imbalance[0], imbalance[1], seed,
+                                      _ptr(scratch), nbytes, _ptr(part), _ptr(med),
+                                      _stream(stream)))
+        self._scratch = scratch
+        return part, med
+
+    def search_partitioned(self, q: torch.Tensor, keys: torch.Tensor, part: torch.Tensor,
+                           p: int, stream=None):
+        """Search every part separately, keep the k best; returns (ids, d, evals)."""
+        q = self._as_points(q)
+        m = q.shape[0]
+        keys = keys.to(device=self.device, dtype=torch.int64).contiguous()
+        part = part.to(device=self.device, dtype=torch.int32).contiguous()
+        nbytes = _lib.lib.knng_search_partitioned_scratch_bytes(self._h, m, p)
+        scratch = _aligned_buffer(max(nbytes, 256), self.device)
+        ids = torch.empty((m, self.cfg.k), dtype=torch.int32, device=self.device)
+        d = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device)
+        ev = torch.empty(m, dtype=torch.int32, device=self.device)
+        check(_lib.lib.knng_search_partitioned(self._h, _ptr(q), m, _ptr(keys), _ptr(part), p,
+                                               _ptr(scratch), nbytes, _ptr(ids), _ptr(d),
+                                               _ptr(ev), _stream(stream)))
+        self._scratch = scratch
+        return ids, d, ev
+
     def query(self, q: torch.Tensor, list_reads: bool = False, stream=None):
         """Read-only k-nn query; returns (ids, d, evals[, list_reads])."""
         q = self._as_points(q)

@@ -267,7 +267,8 @@ knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_
  * with iGNNS in every part separately -- within a part, nodes of other parts
  * are never drawn, evaluated or counted, and the budget is B(n_t) of the
  * part's size -- and the k best of the p partial results are returned.  All
- * m * p searches run in one launch.  uint8 graphs.
+ * m * p searches run in one launch.  uint8 graphs, or float graphs with
+ * KNNG_SCORE_EXACT (not with the cosine metric).
  *  part_dev      [n] int32 part of each node (0 .. p-1), e.g. from
  *                knng_partition.
  *  scratch_dev   knng_search_partitioned_scratch_bytes(g, m, p) bytes.

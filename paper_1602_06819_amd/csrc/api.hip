@@ -1038,7 +1038,10 @@ knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
   if (m < 0 || m * (int64_t)p >= ((int64_t)1 << 31))
     return fail(KNNG_EINVAL, "m * p must be below 2^31");
   if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
-  if (g->S.is_float) return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs");
+  if (g->S.is_float && g->S.format != ROW_F32)
+    return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs and float graphs "
+                             "with float32 scoring");
+  if (g->S.cosine) return fail(KNNG_EINVAL, "partitioned search does not take the cosine metric");
   knng_status s;
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
@@ -1081,6 +1084,11 @@ knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
   if (search_sets_global(g->n)) {
     a.gvis = at<uint32_t>(g->ws, W.off_sets);
     a.gvis_slots = W.set_slots;
+  }
+  if (S.is_float) {
+    a.master = at<float>(g->st, S.off_master);
+    a.master_stride = S.mstride;
+    a.master_chunks = S.mstride / 4;
   }
   a.node_part = part_dev;
   a.nparts = p;

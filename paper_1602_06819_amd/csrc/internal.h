@@ -231,6 +231,8 @@ hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, 
 hipError_t launch_search_f32(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds);
 hipError_t launch_search_f32_gnns(const SearchArgs& a, hipStream_t s, unsigned grid,
                                   size_t lds);
+hipError_t launch_search_f32_part(const SearchArgs& a, hipStream_t s, unsigned grid,
+                                  size_t lds);
 hipError_t launch_peers(const PeerArgs& a, hipStream_t s);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);

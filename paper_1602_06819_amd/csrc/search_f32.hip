@@ -30,4 +30,16 @@ hipError_t launch_search_f32_gnns(const SearchArgs& a, hipStream_t s, unsigned g
   return hipErrorInvalidValue;
 }
 
+// Partitioned search on float32 rows.
+hipError_t launch_search_f32_part(const SearchArgs& a, hipStream_t s, unsigned grid,
+                                  size_t lds) {
+  if (a.dim <= 64)
+    return launch_search_t<ScoreF32<4, 4>, 4, 4, 1, 8, 4, false, true>(a, s, grid, lds);
+  if (a.dim <= 128)
+    return launch_search_t<ScoreF32<8, 4>, 8, 4, 2, 4, 8, false, true>(a, s, grid, lds);
+  if (a.dim <= 256)
+    return launch_search_t<ScoreF32<16, 4>, 16, 4, 4, 2, 16, false, true>(a, s, grid, lds);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace knng

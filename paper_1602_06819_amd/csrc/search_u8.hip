@@ -58,7 +58,8 @@ hipError_t launch_search_part(const SearchArgs& a0, hipStream_t s) {
   SearchArgs a = a0;
   a.m = a.rows[0].count + a.rows[1].count;
   if (a.m <= 0) return hipSuccess;
-  if (a.format != ROW_I8 || a.nparts < 1 || !a.node_part || !a.part_budget)
+  if ((a.format != ROW_I8 && a.format != ROW_F32) || a.nparts < 1 || !a.node_part ||
+      !a.part_budget)
     return hipErrorInvalidValue;
   a.vis_words = (int32_t)((a.n + 31) / 32);
   a.vis_words_pad = (int32_t)round_up(a.vis_words, 4);
@@ -68,6 +69,7 @@ hipError_t launch_search_part(const SearchArgs& a0, hipStream_t s) {
   if (gvis && grid > a.gvis_slots) grid = a.gvis_slots;
   if (grid < 1) return hipErrorInvalidValue;
   const unsigned gr = (unsigned)grid;
+  if (a.format == ROW_F32) return launch_search_f32_part(a, s, gr, lds);
   const int chunks = a.row_bytes / 16;
   if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1, 1, false, true>(a, s, gr, lds);
   if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1, 2, false, true>(a, s, gr, lds);

@@ -10,6 +10,10 @@ library on the synthetic stand-ins:
   depth      correct edges and similarities of sequential online building
              against the update depth 1..5 (Section 8.3: n = 1,000 initial
              points, n_a = 1,000 added, speedup 20)
+  partitions recall of the partitioned search (balanced k-medoids parts,
+             each searched with its own budget, k best of the union) against
+             the number of parts, beside the plain search (Section 8.4:
+             graph of 8,000 points, speedup 4, 100 queries, 10 repetitions)
   quality    the quality Q of the online graph over the insertion of
              n_a = 16,000 points into n = 8,000 (Section 8.5.2, speedup 4;
              one partition)
@@ -109,6 +113,25 @@ def run_gnns(w, n, m, e, speedups, restarts, reps):
                "recall": float(np.mean(rec))}
 
 
+def run_partitions(w, n, m, speedup, parts, reps):
+    from .graph import KnnGraph
+    for p in parts:
+        rec, seq_rec, ev_all = [], [], []
+        for rep in range(reps):
+            Xd, ids, d, keys, gt = _setup_search(w, n, m, rep)
+            g = KnnGraph.load(_graph_cfg(w, n, m, speedup=speedup), Xd[:n], ids, d)
+            if p == 1:
+                r, _, ev, _ = g.search(Xd[n:], keys)
+            else:
+                part, _ = g.partition(p, iters=5, seed=rep)
+                r, _, ev = g.search_partitioned(Xd[n:], keys, part, p)
+            rec.append(_recall(r.cpu().numpy(), gt, w.k))
+            ev_all.append(float(ev.float().mean()))
+        yield {"experiment": "partitions", "workload": w.name, "n": n, "speedup": speedup,
+               "parts": p, "recall": float(np.mean(rec)), "similarities": float(np.mean(ev_all)),
+               "reps": reps}
+
+
 def run_depth(w, n, n_a, speedup, depths):
     import torch
     from . import metrics
@@ -160,7 +183,7 @@ def run_quality(w, n, n_a, speedup, checkpoints, batch):
 def main(argv=None):
     from datagen import get_workload
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["expansion", "gnns", "depth", "quality"])
+    ap.add_argument("experiment", choices=["expansion", "gnns", "depth", "quality", "partitions"])
     ap.add_argument("--workload", default="f32-d3-gmm")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--n-add", type=int, default=None)
@@ -177,6 +200,9 @@ def main(argv=None):
     elif args.experiment == "gnns":
         it = run_gnns(w, args.n or 5000, args.queries, args.e, [2, 4, 8, 16, 32, 64, 128],
                       [1, 2, 4, 8, 16, 32, 64, 128], args.reps)
+    elif args.experiment == "partitions":
+        it = run_partitions(w, args.n or 8000, args.queries, args.speedup or 4,
+                            [1, 2, 4, 8, 16, 32], args.reps)
     elif args.experiment == "depth":
         it = run_depth(w, args.n or 1000, args.n_add or 1000, args.speedup or 20, [1, 2, 3, 4, 5])
     else:

@@ -83,3 +83,22 @@ def test_partitioned_search_bit_exact(G, p, speedup):
         assert ev[j] == sum(evs), j
         assert ids[j, :len(r.pairs)].tolist() == [v for _, v in r.pairs], j
         assert d[j, :len(r.pairs)].tolist() == [dd for dd, _ in r.pairs], j
+
+
+def test_partitioned_search_float_exhaustive(G):
+    """float32 scoring: with speedup 1 every part is searched exhaustively,
+    so the merged result is the exact top-k."""
+    import torch
+    from datagen import float_mixture
+    n, dim, k, p = 2000, 3, 10, 4
+    X = float_mixture(99, 10, dim).sample(n + 40, 1099).astype(np.float32)
+    cfg = G.GraphConfig(dim=dim, k=k, capacity=n, max_batch=64, speedup=1, dtype="f32",
+                        score="exact")
+    g = G.KnnGraph.build_exact(cfg, tensor(X[:n]))
+    part, _ = g.partition(p, iters=3, seed=1)
+    keys = torch.arange(0, 40, dtype=torch.int64)
+    ids, d, ev = g.search_partitioned(tensor(X[n:]), keys, part, p)
+    assert np.all(ev.cpu().numpy() == n)
+    rows = O.ExactRows(X[:n], k)
+    ref = np.array([[dd for dd, _ in rows.row(q)] for q in X[n:]])
+    assert np.isclose(d.cpu().numpy().astype(np.float64), ref, rtol=2e-5, atol=1e-12).all()

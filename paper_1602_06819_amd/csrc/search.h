@@ -281,11 +281,17 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       Aj = 1u;
       Cj = 0u;
     }
-    uint32_t Ag[G], Cg[G];           // the same for this lane's group candidates
+    // The same for this lane's group candidates.  Wide groups (16 lanes
+    // per row, 16 passes) take the group-view positions from the lane view
+    // with one shuffle per pass instead, which keeps 32 registers free.
+    constexpr bool KEEP_AC = G < 16;
+    uint32_t Ag[KEEP_AC ? G : 1], Cg[KEEP_AC ? G : 1];
+    if constexpr (KEEP_AC) {
 #pragma unroll
-    for (int p = 0; p < G; ++p) {
-      Ag[p] = G == 1 ? Aj : shfl_u32(Aj, p * SLOTS + slot);
-      Cg[p] = G == 1 ? Cj : shfl_u32(Cj, p * SLOTS + slot);
+      for (int p = 0; p < G; ++p) {
+        Ag[p] = G == 1 ? Aj : shfl_u32(Aj, p * SLOTS + slot);
+        Cg[p] = G == 1 ? Cj : shfl_u32(Cj, p * SLOTS + slot);
+      }
     }
 
     uint64_t rk = KEY_INF;          // result list: lane j < kk holds the j-th best
@@ -315,7 +321,11 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 #pragma unroll
       for (int p = 0; p < G; ++p) {
         const uint32_t c = (uint32_t)(p * SLOTS + slot);
-        const uint32_t xg = (Ag[p] * xP + Cg[p]) & mmask;
+        uint32_t xg;
+        if constexpr (KEEP_AC)
+          xg = (Ag[p] * xP + Cg[p]) & mmask;
+        else
+          xg = shfl_u32(xL, (int)c);
         cidG[p] = (P + c < a.m_mod && xg < n) ? (int32_t)xg : -1;
       }
     };

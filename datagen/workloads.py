@@ -116,7 +116,7 @@ WORKLOADS: dict[str, Workload] = {
         name="f32-d960-n500k-b512-fp8", kind="f32", dim=960, k=50, n_initial=500_000,
         n_insert=20_000, batch=512, n_query=0, n_clusters=500, lognormal_dim_scale=1.0,
         mixture_seed=51, stream_seed=52, query_seed=53,
-        speedup=100, expansion_num=5, expansion_den=1, depth=2, score="fp8"),
+        speedup=5, expansion_num=3, expansion_den=2, depth=2, score="fp8"),
 }
 
 

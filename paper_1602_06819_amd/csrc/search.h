@@ -50,7 +50,7 @@ struct ScoreI8 {
   static constexpr bool kSide = false;
   v4i q[CPL];
   int32_t qq;
-  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     const int sub = lane_id() % G;
     int nrm = 0;
     if (r.qvec) {
@@ -84,7 +84,7 @@ struct ScoreI8 {
       for (int e = 0; e < 4; ++e) nrm = __builtin_amdgcn_sdot4(q[pp][e], q[pp][e], nrm, false);
     qq = group_sum<G>(nrm);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     int xx = 0, qx = 0;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -98,7 +98,7 @@ struct ScoreI8 {
     return (uint32_t)(qq + xx - 2 * qx);
   }
   // expansion test: keep r iff e_den (1 + d_r) <= e_num (1 + best)
-  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return !((int64_t)den * (1 + (int64_t)d) > (int64_t)num * (1 + (int64_t)best));
   }
 };
@@ -126,10 +126,10 @@ template <int G, int CPL>
 struct ScoreBF16 {
   static constexpr bool kSide = false;
   float q[CPL][8];
-  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 8>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     float s = 0.f;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -143,7 +143,7 @@ struct ScoreBF16 {
       }
     return __float_as_uint(group_sum<G>(s));
   }
-  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return keep_f32(d, best, num, den);
   }
 };
@@ -153,10 +153,10 @@ template <int G, int CPL>
 struct ScoreFP8 {
   static constexpr bool kSide = true;    // the row scale
   float q[CPL][16];
-  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 16>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t side) const {
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t side) const {
     const float scale = __uint_as_float(side);
     float s = 0.f;
 #pragma unroll
@@ -172,7 +172,7 @@ struct ScoreFP8 {
       }
     return __float_as_uint(group_sum<G>(s));
   }
-  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return keep_f32(d, best, num, den);
   }
 };
@@ -181,10 +181,10 @@ template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kSide = false;
   float q[CPL][4];
-  __device__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
   }
-  __device__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     float s = 0.f;
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
@@ -195,7 +195,7 @@ struct ScoreF32 {
       }
     return __float_as_uint(group_sum<G>(s));
   }
-  __device__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return keep_f32(d, best, num, den);
   }
 };
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     v4i lv[NB][PB][LCPL];           // gathered adjacency rows
     uint32_t sv[NB][PB];            // per-row side value (FP8 scale)
 
-    auto window = [&]() {
+    auto window = [&]() __attribute__((always_inline)) {
       xL = (Aj * xP + Cj) & mmask;
       cidL = (P + (uint32_t)lane < a.m_mod && xL < n) ? (int32_t)xL : -1;
 #pragma unroll
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         cidG[p] = (P + c < a.m_mod && xg < n) ? (int32_t)xg : -1;
       }
     };
-    auto issue_group = [&](int gi, int buf) {
+    auto issue_group = [&](int gi, int buf) __attribute__((always_inline)) {
 #pragma unroll
       for (int q = 0; q < PB; ++q) {
         const int p = gi * PB + q;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         }
       }
     };
-    auto issue = [&]() {
+    auto issue = [&]() __attribute__((always_inline)) {
       if (PART) partL = cidL >= 0 ? a.node_part[cidL] : -1;
       issue_group(0, 0);
     };
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       // than G, only those passes are computed.
       uint32_t dg[G];
       uint32_t d = 0xffffffffu;
-      auto pass = [&](int p, int buf, int q) {
+      auto pass = [&](int p, int buf, int q) __attribute__((always_inline)) {
         const int c = p * SLOTS + slot;
         if (LISTS) {
 #pragma unroll
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         const uint32_t dd = sc.dist(xv[buf][q], Score::kSide ? sv[buf][q] : 0u);
         dg[p] = cidG[p] >= 0 ? dd : 0xffffffffu;
       };
-      auto to_lane = [&](int p) {
+      auto to_lane = [&](int p) __attribute__((always_inline)) {
         const int j = lane - p * SLOTS;
         const bool mine = j >= 0 && j < SLOTS;
         const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? j * G : 0);

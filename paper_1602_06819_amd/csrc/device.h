@@ -103,12 +103,19 @@ __device__ __forceinline__ uint32_t f32_to_bf16(float x) {
 }
 
 // OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; no
-// infinities, 0x7f / 0xff are NaN; largest finite 448) -> float.
-__device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
-  uint32_t s = (b >> 7) & 1u, e = (b >> 3) & 15u, m = b & 7u;
-  float v = e == 0 ? (float)m * 0.001953125f                 // m * 2^-9 (subnormal)
-                   : __uint_as_float(((e + 120u) << 23) | (m << 20));   // 2^(e-7) (1 + m/8)
-  return s ? -v : v;
+// infinities, 0x7f / 0xff are NaN; largest finite 448): the four codes of a
+// 32-bit word (byte t = element t) -> float, by gfx950's packed conversion,
+// which reads OCP E4M3 and is exact (every E4M3 value is a float; checked
+// against the definition for all 254 finite codes).  The library never
+// stores a NaN code (its quantizer saturates at 448).
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void e4m3x4_to_f32(uint32_t w, float (&v)[4]) {
+  const v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  const v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  v[0] = lo.x;
+  v[1] = lo.y;
+  v[2] = hi.x;
+  v[3] = hi.y;
 }
 
 // float -> OCP FP8 E4M3, round to nearest even, saturating to +-448.

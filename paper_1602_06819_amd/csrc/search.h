@@ -163,10 +163,11 @@ struct ScoreFP8 {
     for (int pp = 0; pp < CPL; ++pp)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        uint32_t w = (uint32_t)x[pp][e];
+        float v[4];
+        e4m3x4_to_f32((uint32_t)x[pp][e], v);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const float d = __builtin_fmaf(-scale, e4m3_to_f32((w >> (8 * t)) & 0xffu), q[pp][4 * e + t]);
+          const float d = __builtin_fmaf(-scale, v[t], q[pp][4 * e + t]);
           s = __builtin_fmaf(d, d, s);
         }
       }

@@ -254,8 +254,11 @@ def main():
     if not args.no_recall:
         n_final = n0 + inserts
         ids_online, _ = g.lists()
+        # the exact graph is built from the float32 rows whatever the scoring
+        # format; float32 scoring rows exist up to d = 256
+        gt_score = "exact" if not is_float or w.dim <= 256 else w.score
         cfg_x = GraphConfig(dim=w.dim, k=w.k, capacity=n_final, max_batch=b, speedup=speedup,
-                            dtype=gdt, score="exact")
+                            dtype=gdt, score=gt_score)
         gx = KnnGraph.build_exact(cfg_x, Xd[:n_final])
         ids_exact, _ = gx.lists()
         io = ids_online.cpu().numpy()

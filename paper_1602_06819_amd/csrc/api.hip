@@ -237,7 +237,10 @@ StorageLayout storage_layout(const knng_params& p) {
     S.off_vec = S.off_master;
   else
     S.off_vec = take(cur, (size_t)S.cap * S.row_bytes);
-  if (S.format == ROW_FP8) S.off_scale = take(cur, (size_t)S.cap * 4);
+  if (S.format == ROW_FP8) {
+    S.off_scale = take(cur, (size_t)S.cap * 4);
+    S.off_qnorm = take(cur, (size_t)S.cap * 4);
+  }
   S.off_norms = take(cur, (size_t)S.cap * 4);
   S.off_ids = take(cur, (size_t)S.cap * S.k_pad * 4);
   S.off_dist = take(cur, (size_t)S.cap * S.k_pad * 4);
@@ -348,6 +351,7 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.vec = at<char>(g->st, S.off_vec);
   a.row_bytes = S.row_bytes;
   a.side = S.format == ROW_FP8 ? at<uint32_t>(g->st, S.off_scale) : nullptr;
+  a.side2 = S.format == ROW_FP8 ? at<uint32_t>(g->st, S.off_qnorm) : nullptr;
   if (S.is_float) {
     a.master = at<float>(g->st, S.off_master);
     a.master_stride = S.mstride;
@@ -462,6 +466,7 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipSt
     a.norms = at<float>(g->st, S.off_norms) + first;
     a.score = S.format == ROW_F32 ? nullptr : at<char>(g->st, S.off_vec) + first * S.row_bytes;
     a.scale = S.format == ROW_FP8 ? at<float>(g->st, S.off_scale) + first : nullptr;
+    a.qnorm = S.format == ROW_FP8 ? at<float>(g->st, S.off_qnorm) + first : nullptr;
     a.m = m;
     a.dim = S.dim;
     a.stride = S.mstride;

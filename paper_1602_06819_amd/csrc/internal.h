@@ -33,8 +33,8 @@ struct StorageLayout {
   bool cosine = false; // rows normalized to unit length (cosine metric)
   int32_t pad = 0;     // distance padding pattern
   int64_t cap = 0;
-  size_t off_vec = 0, off_scale = 0, off_master = 0, off_norms = 0, off_ids = 0, off_dist = 0,
-         off_head = 0, total = 0;
+  size_t off_vec = 0, off_scale = 0, off_qnorm = 0, off_master = 0, off_norms = 0, off_ids = 0,
+         off_dist = 0, off_head = 0, total = 0;
 };
 
 // Workspace (calls of up to M points):
@@ -83,6 +83,7 @@ struct IngestF32Args {
   float* norms;        // [m]
   char* score;         // [m][row_bytes] (BF16 / FP8 formats)
   float* scale;        // [m] (FP8)
+  float* qnorm;        // [m] (FP8): squared norm of the quantized row, scale^2 sum v^2
   int64_t m;
   int dim, stride, row_bytes, format;
   int cosine;          // normalize rows to unit length first
@@ -125,6 +126,7 @@ struct SearchArgs {
   int format;                              // RowFormat of vec
   const void* vec; int row_bytes;          // scoring rows
   const uint32_t* side;                    // per-row value: int8 norms, FP8 scales
+  const uint32_t* side2;                   // second per-row value: FP8 quantized norms
   const float* master; int master_stride; int master_chunks;   // float graphs (re-rank)
   const int32_t* nbr_ids; int k, k_pad;
   int keep;              // result entries kept by the search (k, more before a re-rank)

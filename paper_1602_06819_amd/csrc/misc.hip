@@ -103,9 +103,20 @@ __global__ __launch_bounds__(256) void k_ingest_f32(IngestF32Args a) {
   } else if (a.format == ROW_FP8) {
     const float scale = mx / 448.f;
     uint8_t* frow = reinterpret_cast<uint8_t*>(a.score + row * a.row_bytes);
-    for (int j = lane; j < a.row_bytes; j += WAVE)
-      frow[j] = (uint8_t)((j < a.dim && scale > 0.f) ? f32_to_e4m3(value(j) / scale) : 0u);
-    if (lane == 0) a.scale[row] = scale;
+    float qn = 0.f;                                // sum of the decoded codes squared
+    for (int j = lane; j < a.row_bytes; j += WAVE) {
+      const uint32_t c = (j < a.dim && scale > 0.f) ? f32_to_e4m3(value(j) / scale) : 0u;
+      frow[j] = (uint8_t)c;
+      float v[4];
+      e4m3x4_to_f32(c, v);
+      qn = __builtin_fmaf(v[0], v[0], qn);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) qn += __shfl_xor(qn, off, WAVE);
+    if (lane == 0) {
+      a.scale[row] = scale;
+      a.qnorm[row] = scale * scale * qn;
+    }
   }
 }
 

@@ -6,6 +6,8 @@
 //   ScoreFP8   FP8 E4M3 rows with one float32 scale s per row:
 //              sum of (q - s x)^2 in float32
 //   ScoreF32   float32 rows: sum of (q - x)^2 in float32
+//   ScoreFP8M  FP8 rows of 257-1024 coordinates on the matrix cores:
+//              |q|^2 - 2 s q.v + s^2 sum v^2 from FP8 MFMA dot products
 //
 // Sequential semantics on a 64-lane wavefront.  Restart nodes are drawn one
 // at a time and tested, and the eager climb moves to the *first* improving
@@ -25,7 +27,8 @@
 // c in lane c: sequential-order decisions with ballots) and the "group
 // view" (candidate p * SLOTS + g handled by lane group g in pass p: the
 // gathers and dot products; a group of G lanes reads one row, 16 bytes per
-// lane per load, CPL loads per lane).
+// lane per load, CPL loads per lane).  Groups are lanes g*G .. g*G+G-1, or
+// for the MFMA score lanes g, g+16, g+32, g+48 (the operand layout).
 //
 // Latency.  A batch gives one wavefront per query, so its time is the
 // length of the slowest query's chain of dependent steps.  Every candidate's
@@ -48,6 +51,7 @@ namespace knng {
 template <int G, int CPL>
 struct ScoreI8 {
   static constexpr bool kSide = false;
+  static constexpr bool kSide2 = false, kMfma = false;
   v4i q[CPL];
   int32_t qq;
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
@@ -125,6 +129,7 @@ __device__ __forceinline__ bool keep_f32(uint32_t d, uint32_t best, int num, int
 template <int G, int CPL>
 struct ScoreBF16 {
   static constexpr bool kSide = false;
+  static constexpr bool kSide2 = false, kMfma = false;
   float q[CPL][8];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 8>(a, r, qi, q);
@@ -152,6 +157,7 @@ struct ScoreBF16 {
 template <int G, int CPL>
 struct ScoreFP8 {
   static constexpr bool kSide = true;    // the row scale
+  static constexpr bool kSide2 = false, kMfma = false;
   float q[CPL][16];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 16>(a, r, qi, q);
@@ -181,6 +187,7 @@ struct ScoreFP8 {
 template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kSide = false;
+  static constexpr bool kSide2 = false, kMfma = false;
   float q[CPL][4];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
@@ -195,6 +202,85 @@ struct ScoreF32 {
         s = fmaf(d0, d0, s);
       }
     return __float_as_uint(group_sum<G>(s));
+  }
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return keep_f32(d, best, num, den);
+  }
+};
+
+// FP8 rows scored on the matrix cores.  One 16x16x128 FP8 MFMA multiplies a
+// 16-row A operand by 16 candidate rows over 128 coordinates; A holds the
+// query in row 0 and zeros elsewhere, so one instruction gives the query's
+// dot products with 16 candidates.  Lane l serves candidate l % 16 (the
+// slot) and coordinate group l / 16 (the sub): the two operands pair their
+// bytes lane group by lane group, so the query and the rows use the same
+// chunk of coordinates per lane.  The query is encoded in two FP8 terms,
+// q ~ sq (h + l / 16), which keeps about 8 significant bits; the row term
+// s^2 sum v^2 is stored at ingest.  The score is |q|^2 - 2 s q.v + s^2 sum
+// v^2, i.e. |q - s v|^2 up to rounding (the MFMA's internal sum is not an
+// exact float32 sum), clamped at 0; it is valid in the candidates' sub-0
+// lanes 0-15.
+template <int CPL>
+struct ScoreFP8M {
+  static_assert(CPL % 2 == 0, "an MFMA step takes two 16-byte chunks per lane");
+  static constexpr bool kSide = true, kSide2 = true, kMfma = true;
+  static constexpr int G = 4;
+  v4i qh[CPL], ql[CPL];
+  float qq;                       // |q|^2
+  float qs;                       // the query's code scale sq
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+    const int lane = lane_id();
+    const int slot = lane % 16, sub = lane / 16;
+    const float* qr = (const float*)r.qraw + (int64_t)qi * a.dim;
+    float nrm = 0.f, mx = 0.f;
+    for (int j = lane; j < a.dim; j += WAVE) {
+      const float v = qr[j];
+      nrm = __builtin_fmaf(v, v, nrm);
+      mx = fmaxf(mx, fabsf(v));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      nrm += __shfl_xor(nrm, off, WAVE);
+      mx = fmaxf(mx, __shfl_xor(mx, off, WAVE));
+    }
+    qq = nrm;
+    qs = mx / 448.f;
+    // encode the coordinates into LDS, then take this lane's chunks from there
+    __shared__ __align__(16) uint8_t qhb[64 * CPL], qlb[64 * CPL];
+    for (int j = lane; j < 64 * CPL; j += WAVE) {
+      const float v = (j < a.dim && qs > 0.f) ? qr[j] / qs : 0.f;
+      const uint32_t h = f32_to_e4m3(v);
+      float hv[4];
+      e4m3x4_to_f32(h, hv);
+      qhb[j] = (uint8_t)h;
+      qlb[j] = (uint8_t)f32_to_e4m3((v - hv[0]) * 16.f);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp) {
+      const int c0 = 16 * (sub + G * pp);
+      qh[pp] = slot == 0 ? *reinterpret_cast<const v4i*>(qhb + c0) : v4i{0, 0, 0, 0};
+      ql[pp] = slot == 0 ? *reinterpret_cast<const v4i*>(qlb + c0) : v4i{0, 0, 0, 0};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t side,
+                                           uint32_t side2) const {
+    v4f ah = {0.f, 0.f, 0.f, 0.f}, al = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < CPL / 2; ++i) {
+      const v8i b = __builtin_shufflevector(x[2 * i], x[2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+      const v8i h = __builtin_shufflevector(qh[2 * i], qh[2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+      const v8i l = __builtin_shufflevector(ql[2 * i], ql[2 * i + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+      // format 0 (FP8 E4M3) for both operands, unit block scales (E8M0 127)
+      ah = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(h, b, ah, 0, 0, 0, 127, 0, 127);
+      al = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(l, b, al, 0, 0, 0, 127, 0, 127);
+    }
+    const float dot = qs * __builtin_fmaf(al[0], 0.0625f, ah[0]);   // q . v
+    const float d = __builtin_fmaf(-2.f * __uint_as_float(side), dot, qq + __uint_as_float(side2));
+    return __float_as_uint(d > 0.f ? d : 0.f);
   }
   __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return keep_f32(d, best, num, den);
@@ -235,8 +321,11 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   constexpr int LCH = LISTS ? LROW / 4 : 1;       // 16-byte chunks of a staged row
   constexpr int LCPL = (LCH + G - 1) / G;         // list chunks per lane
   const int lane = threadIdx.x;
-  const int slot = lane / G;
-  const int sub = lane % G;
+  // lane -> (candidate slot, lane in the row group): row-major groups of G
+  // lanes, or column-major for the MFMA score (candidate = lane % SLOTS)
+  constexpr bool CM = Score::kMfma;
+  const int slot = CM ? lane % SLOTS : lane / G;
+  const int sub = CM ? lane / SLOTS : lane % G;
   const uint32_t mmask = a.m_mod - 1u;
   const uint32_t n = (uint32_t)a.n;
   int32_t* lists = reinterpret_cast<int32_t*>(lds + (GVIS ? 0 : a.vis_words_pad));
@@ -315,6 +404,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     v4i xv[NB][PB][CPL];            // gathered rows, by buffer and pass in group
     v4i lv[NB][PB][LCPL];           // gathered adjacency rows
     uint32_t sv[NB][PB];            // per-row side value (FP8 scale)
+    uint32_t sv2[NB][PB];           // second side value (FP8 quantized norm)
 
     auto window = [&]() __attribute__((always_inline)) {
       xL = (Aj * xP + Cj) & mmask;
@@ -345,6 +435,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             xv[buf][q][pp] = v4i{0, 0, 0, 0};
         }
         if (Score::kSide) sv[buf][q] = ok ? a.side[cidG[p]] : 0u;
+        if (Score::kSide2) sv2[buf][q] = ok ? a.side2[cidG[p]] : 0u;
         if (PART) pg[p] = ok ? a.node_part[cidG[p]] : -1;
         if (LISTS) {
 #pragma unroll
@@ -395,13 +486,17 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
               *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[buf][q][lc];
           }
         }
-        const uint32_t dd = sc.dist(xv[buf][q], Score::kSide ? sv[buf][q] : 0u);
+        uint32_t dd;
+        if constexpr (Score::kSide2)
+          dd = sc.dist(xv[buf][q], sv[buf][q], sv2[buf][q]);
+        else
+          dd = sc.dist(xv[buf][q], Score::kSide ? sv[buf][q] : 0u);
         dg[p] = cidG[p] >= 0 ? dd : 0xffffffffu;
       };
       auto to_lane = [&](int p) __attribute__((always_inline)) {
         const int j = lane - p * SLOTS;
         const bool mine = j >= 0 && j < SLOTS;
-        const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? j * G : 0);
+        const uint32_t got = (uint32_t)shfl_i32((int)dg[p], mine ? (CM ? j : j * G) : 0);
         if (mine) d = got;
       };
       const int act = climbing ? (a.k + SLOTS - 1) / SLOTS : G;
@@ -483,7 +578,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             climbing = true;
           }
           if (LISTS) {
-            const int fc = spaced ? f / G : f;        // candidate index of lane f
+            const int fc = spaced ? (CM ? f : f / G) : f;   // candidate index of lane f
             if (!climb_spaced) cidL = lane < a.k ? lists[fc * LROW + lane] : -1;
 #pragma unroll
             for (int p = 0; p < G; ++p) {

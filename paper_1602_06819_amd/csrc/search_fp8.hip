@@ -16,10 +16,10 @@ hipError_t launch_search_fp8(const SearchArgs& a, hipStream_t s, unsigned grid, 
   if (a.dim <= 64) return launch_search_t<ScoreFP8<4, 1>, 4, 1, 1, 8>(a, s, grid, lds);
   if (a.dim <= 128) return launch_search_t<ScoreFP8<4, 2>, 4, 2, 2, 4>(a, s, grid, lds);
   if (a.dim <= 256) return launch_search_t<ScoreFP8<4, 4>, 4, 4, 4, 2>(a, s, grid, lds);
-  // long rows (up to 1024 coordinates): 16 lanes per row, 4 chunks per
-  // lane, passes in groups of 2 with double-buffered gathers
-  if (a.dim <= 512) return launch_search_t<ScoreFP8<16, 4>, 16, 4, 8, 1, 2>(a, s, grid, lds);
-  if (a.dim <= 1024) return launch_search_t<ScoreFP8<16, 4>, 16, 4, 16, 1, 2>(a, s, grid, lds);
+  // long rows (up to 1024 coordinates) on the matrix cores: 16 candidates
+  // per pass, 4 lanes per row, one pass (or two) per double-buffered group
+  if (a.dim <= 512) return launch_search_t<ScoreFP8M<8>, 4, 8, 8, 1, 2>(a, s, grid, lds);
+  if (a.dim <= 1024) return launch_search_t<ScoreFP8M<16>, 4, 16, 16, 1, 1>(a, s, grid, lds);
   return hipErrorInvalidValue;
 }
 

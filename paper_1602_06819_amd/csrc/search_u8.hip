@@ -15,16 +15,16 @@ size_t search_lds_bytes(int64_t n, int k_pad, bool global_visited) {
 // fetches 64 / G rows); rows of 33-64 bytes: 2 lanes of 2 chunks (32 rows per
 // pass: a restart window takes 2 passes and fewer group reductions and
 // transposes than with 4 lanes of one chunk, measured 5% faster inserts at
-// d = 64); longer rows (up to 256 bytes): groups of 4 lanes, up to 64 bytes
-// per lane.
+// d = 64); longer rows (up to 256 bytes): 2 lanes of up to 8 chunks (also
+// measured faster than 4 lanes at d = 128 and 256).
 static hipError_t launch_search_i8(const SearchArgs& a, hipStream_t s, unsigned grid,
                                    size_t lds) {
   const int chunks = a.row_bytes / 16;
   if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1>(a, s, grid, lds);
   if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1>(a, s, grid, lds);
   if (chunks <= 4) return launch_search_t<ScoreI8<2, 2>, 2, 2, 0, 1>(a, s, grid, lds);
-  if (chunks <= 8) return launch_search_t<ScoreI8<4, 2>, 4, 2, 0, 1>(a, s, grid, lds);
-  if (chunks <= 16) return launch_search_t<ScoreI8<4, 4>, 4, 4, 0, 1>(a, s, grid, lds);
+  if (chunks <= 8) return launch_search_t<ScoreI8<2, 4>, 2, 4, 0, 1>(a, s, grid, lds);
+  if (chunks <= 16) return launch_search_t<ScoreI8<2, 8>, 2, 8, 0, 1>(a, s, grid, lds);
   return hipErrorInvalidValue;
 }
 
@@ -35,8 +35,8 @@ static hipError_t launch_search_i8_gnns(const SearchArgs& a, hipStream_t s, unsi
   if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1, 1, true>(a, s, grid, lds);
   if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1, 2, true>(a, s, grid, lds);
   if (chunks <= 4) return launch_search_t<ScoreI8<2, 2>, 2, 2, 0, 1, 2, true>(a, s, grid, lds);
-  if (chunks <= 8) return launch_search_t<ScoreI8<4, 2>, 4, 2, 0, 1, 4, true>(a, s, grid, lds);
-  if (chunks <= 16) return launch_search_t<ScoreI8<4, 4>, 4, 4, 0, 1, 4, true>(a, s, grid, lds);
+  if (chunks <= 8) return launch_search_t<ScoreI8<2, 4>, 2, 4, 0, 1, 2, true>(a, s, grid, lds);
+  if (chunks <= 16) return launch_search_t<ScoreI8<2, 8>, 2, 8, 0, 1, 2, true>(a, s, grid, lds);
   return hipErrorInvalidValue;
 }
 
@@ -77,8 +77,8 @@ hipError_t launch_search_part(const SearchArgs& a0, hipStream_t s) {
   if (chunks <= 1) return launch_search_t<ScoreI8<1, 1>, 1, 1, 0, 1, 1, false, true>(a, s, gr, lds);
   if (chunks <= 2) return launch_search_t<ScoreI8<2, 1>, 2, 1, 0, 1, 2, false, true>(a, s, gr, lds);
   if (chunks <= 4) return launch_search_t<ScoreI8<2, 2>, 2, 2, 0, 1, 2, false, true>(a, s, gr, lds);
-  if (chunks <= 8) return launch_search_t<ScoreI8<4, 2>, 4, 2, 0, 1, 4, false, true>(a, s, gr, lds);
-  if (chunks <= 16) return launch_search_t<ScoreI8<4, 4>, 4, 4, 0, 1, 4, false, true>(a, s, gr, lds);
+  if (chunks <= 8) return launch_search_t<ScoreI8<2, 4>, 2, 4, 0, 1, 2, false, true>(a, s, gr, lds);
+  if (chunks <= 16) return launch_search_t<ScoreI8<2, 8>, 2, 8, 0, 1, 2, false, true>(a, s, gr, lds);
   return hipErrorInvalidValue;
 }
 

@@ -662,20 +662,33 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 // of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
 // `vis_lds` is the LDS of the visited set (0 when it is global).
 template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false,
-          bool PART = false>
+          bool PART = false, int KPADS = 7>
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
+  // KPADS: the list strides this instantiation serves (1: 16, 2: 32, 4: 64)
   const bool gvis = a.gvis != nullptr;
 #define KNNG_SEARCH_GO(LR, GV)                                                                 \
   hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART>), dim3(grid), \
                      dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.k_pad == 16) {
-    if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
+    if constexpr ((KPADS & 1) != 0) {
+      if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if (a.k_pad == 32) {
-    if (gvis) KNNG_SEARCH_GO(32, true); else KNNG_SEARCH_GO(32, false);
-  } else if (PB < G) {
-    if (gvis) KNNG_SEARCH_GO(64, true); else KNNG_SEARCH_GO(64, false);
+    if constexpr ((KPADS & 2) != 0) {
+      if (gvis) KNNG_SEARCH_GO(32, true); else KNNG_SEARCH_GO(32, false);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
-    if (gvis) KNNG_SEARCH_GO(0, true); else KNNG_SEARCH_GO(0, false);
+    if constexpr ((KPADS & 4) == 0) {
+      return hipErrorInvalidValue;
+    } else if constexpr (PB < G) {
+      if (gvis) KNNG_SEARCH_GO(64, true); else KNNG_SEARCH_GO(64, false);
+    } else {
+      if (gvis) KNNG_SEARCH_GO(0, true); else KNNG_SEARCH_GO(0, false);
+    }
   }
 #undef KNNG_SEARCH_GO
   return hipGetLastError();

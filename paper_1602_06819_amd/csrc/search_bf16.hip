@@ -2,12 +2,14 @@
 // float32 re-rank of the kept candidates.  Row shapes by dimension (16-byte
 // chunks of a scoring row; groups of G lanes read one row; CPL chunks per
 // lane):
-//   dim <= 64     8 chunks  G 2, CPL 4
-//   dim <= 128   16 chunks  G 2, CPL 8
+//   dim <= 64     8 chunks  G 4, CPL 2 (k <= 16) or G 2, CPL 4
+//   dim <= 128   16 chunks  G 4, CPL 4 (k <= 16) or G 2, CPL 8
 //   dim <= 256   32 chunks  G 4, CPL 8
 //   dim <= 512   64 chunks  G 8, CPL 8, passes in groups of 2
 // (fewer lanes per row with more chunks each: fewer passes, group
-// reductions and transposes per step; measured 10-25% faster searches)
+// reductions and transposes per restart window, measured 10-25% faster
+// with 20-id lists; with lists of up to 16 ids the 4-lane layout scans a
+// list in one pass of 16 with half the work per lane, measured faster)
 // The re-rank uses the layout of the stored float32 distance:
 // ceil(dim / 64) chunks per lane of a 16-lane group.
 #include "search.h"
@@ -15,8 +17,14 @@
 namespace knng {
 
 hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds) {
-  if (a.dim <= 64) return launch_search_t<ScoreBF16<2, 4>, 2, 4, 1, 8>(a, s, grid, lds);
-  if (a.dim <= 128) return launch_search_t<ScoreBF16<2, 8>, 2, 8, 2, 4>(a, s, grid, lds);
+  // lists of up to 16 ids: 4 lanes per row (a list scan is one pass of 16);
+  // longer lists: 2 lanes per row (32 candidates per pass)
+  if (a.dim <= 64)
+    return a.k_pad == 16 ? launch_search_t<ScoreBF16<4, 2>, 4, 2, 1, 8, 4, false, false, 1>(a, s, grid, lds)
+                         : launch_search_t<ScoreBF16<2, 4>, 2, 4, 1, 8, 2, false, false, 6>(a, s, grid, lds);
+  if (a.dim <= 128)
+    return a.k_pad == 16 ? launch_search_t<ScoreBF16<4, 4>, 4, 4, 2, 4, 4, false, false, 1>(a, s, grid, lds)
+                         : launch_search_t<ScoreBF16<2, 8>, 2, 8, 2, 4, 2, false, false, 6>(a, s, grid, lds);
   if (a.dim <= 256) return launch_search_t<ScoreBF16<4, 8>, 4, 8, 4, 2>(a, s, grid, lds);
   // long rows (up to 512 coordinates): 8 lanes per row, 8 chunks per
   // lane, passes in groups of 2 with double-buffered gathers

@@ -76,10 +76,16 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
   }
 
   uint64_t L[QT][KM];
+  // distance bits of each list's last entry: candidates above it cannot
+  // enter, so most int8 candidates are rejected by one 32-bit compare before
+  // a key is built
+  uint32_t thr[QT];
 #pragma unroll
-  for (int t = 0; t < QT; ++t)
+  for (int t = 0; t < QT; ++t) {
+    thr[t] = 0xffffffffu;
 #pragma unroll
     for (int j = 0; j < KM; ++j) L[t][j] = KEY_INF;
+  }
 
   for (int32_t d0 = d_begin; d0 < d_end; d0 += 16 * DT) {
     vec4 av[DT][NCH];
@@ -130,11 +136,18 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          int32_t orow = d0 + 16 * dt + 4 * grp + rr;
-          bool ok = orow < d_end &&
-                    !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t]);
-          uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
-          if (key < L[t][KM - 1]) reg_list_insert<KM>(L[t], key);
+          // (the screen pays on the int8 tiles; on the float32 tiles the
+          // branch costs more than it saves, measured)
+          if (F32 || dist[rr] <= thr[t]) {
+            int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+            bool ok = orow < d_end &&
+                      !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t]);
+            uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
+            if (key < L[t][KM - 1]) {
+              reg_list_insert<KM>(L[t], key);
+              if constexpr (!F32) thr[t] = key_dist(L[t][KM - 1]);
+            }
+          }
         }
       }
     }

@@ -46,22 +46,6 @@ __global__ __launch_bounds__(64) void k_peers(PeerArgs a) {
 }
 
 // ---- update proposals ------------------------------------------------------
-__device__ __forceinline__ void emit_proposal(const UpdateArgs& a, int32_t u, int32_t d,
-                                              int32_t src) {
-  int32_t slot = atomicAdd(&a.counters[0], 1);
-  int32_t prev = atomicExch(&a.head[u], slot);
-  Proposal p;
-  p.target = u;
-  p.dist = d;
-  p.src = src;
-  p.next = prev;
-  a.props[slot] = p;
-  if (prev == -1) {
-    int32_t t = atomicAdd(&a.counters[1], 1);
-    a.touched[t] = u;
-  }
-}
-
 // One wavefront per new point.  Level 1 is the point's search result (its
 // distances are reused); level l + 1 is the union of the pre-batch lists of
 // the level-l nodes.  The processed set is a bitset over the snapshot (in
@@ -79,6 +63,12 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
                            : reinterpret_cast<int32_t*>(lds + (GSET ? 0 : a.set_words_pad));
   int32_t* nxt = front + a.front_cap;
   __shared__ int32_t next_count;
+  // Proposals are staged here and bucketed in bulk: one reservation of
+  // proposal slots per flush instead of a dependent atomic per proposal.
+  // The merge orders each bucket by (distance, id), so the order in which
+  // proposals are bucketed never reaches the result.
+  constexpr int PCAP = 512;
+  __shared__ int32_t st_u[PCAP], st_d[PCAP];
   const int lane = threadIdx.x;
   const int32_t i = blockIdx.x;
   if (i >= a.b) return;
@@ -92,6 +82,55 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
   }
   __syncthreads();
 
+  int staged = 0;                          // (uniform) proposals in the buffer
+  auto flush = [&]() __attribute__((always_inline)) {
+    if (staged == 0) return;
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&a.counters[0], staged);
+    base = __shfl(base, 0, WAVE);
+    for (int j0 = 0; j0 < staged; j0 += WAVE) {
+      const int j = j0 + lane;
+      const bool have = j < staged;
+      int32_t u = 0, prev = 0;
+      if (have) {
+        u = st_u[j];
+        const int32_t slot = base + j;
+        prev = atomicExch(&a.head[u], slot);
+        Proposal pr;
+        pr.target = u;
+        pr.dist = st_d[j];
+        pr.src = src;
+        pr.next = prev;
+        a.props[slot] = pr;
+      }
+      // targets whose bucket this proposal opened
+      const uint64_t first = ballot(have && prev == -1);
+      if (first) {
+        int32_t tb = 0;
+        if (lane == 0) tb = atomicAdd(&a.counters[1], __popcll(first));
+        tb = __shfl(tb, 0, WAVE);
+        if (have && prev == -1) a.touched[tb + rank_below(first)] = u;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    staged = 0;
+  };
+  auto stage = [&](bool emit, int32_t u, int32_t d) __attribute__((always_inline)) {
+    const uint64_t m = ballot(emit);
+    const int cnt = __popcll(m);
+    if (cnt == 0) return;
+    if (staged + cnt > PCAP) flush();
+    if (emit) {
+      const int r = staged + rank_below(m);
+      st_u[r] = u;
+      st_d[r] = d;
+    }
+    staged += cnt;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+
   // level 1: the search result, distances reused
   int32_t u = -1, du = 0;
   if (lane < a.k) {
@@ -99,10 +138,8 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
     du = a.res_d[(int64_t)i * a.k_pad + lane];
   }
   bool fresh1 = u >= 0 && bit_set(done_bits, u);
-  if (fresh1) {
-    int32_t thr = a.nbr_d[(int64_t)u * a.k_pad + a.k - 1];
-    if (du < thr) emit_proposal(a, u, du, src);
-  }
+  int32_t thr1 = fresh1 ? a.nbr_d[(int64_t)u * a.k_pad + a.k - 1] : 0;
+  stage(fresh1 && du < thr1, u, du);
   uint64_t m1 = ballot(fresh1);
   if (fresh1) front[rank_below(m1)] = u;
   int fcount = __popcll(m1);
@@ -117,23 +154,28 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
       if (lane == 0) next_count = 0;
       __syncthreads();
       const int total = fcount * a.k;
-      for (int c0 = 0; c0 < total; c0 += WAVE) {
-        int c = c0 + lane;
-        int t = c / a.k;
-        int sidx = c - t * a.k;
+      // list entries of chunk c0 (candidate c = list slot c mod k of front
+      // node c / k), fetched one chunk ahead of their evaluation
+      auto fetch = [&](int c0) __attribute__((always_inline)) {
+        const int c = c0 + lane;
         int32_t w = -1;
         if (c < total) {
-          int32_t ut = front[t];
-          w = a.nbr_ids[(int64_t)ut * a.k_pad + sidx];
+          const int t = c / a.k;
+          w = a.nbr_ids[(int64_t)front[t] * a.k_pad + (c - t * a.k)];
         }
+        return w;
+      };
+      int32_t w_next = total > 0 ? fetch(0) : -1;
+      for (int c0 = 0; c0 < total; c0 += WAVE) {
+        const int32_t w = w_next;
+        if (c0 + WAVE < total) w_next = fetch(c0 + WAVE);
         bool fresh = w >= 0 && bit_set(done_bits, w);
+        // the target's current k-th distance travels with its row
+        const int32_t thr = fresh ? a.nbr_d[(int64_t)w * a.k_pad + a.k - 1] : 0;
         __syncthreads();
         int cnt = total - c0 < WAVE ? total - c0 : WAVE;
         int32_t d = (int32_t)ev.dist(a.vec, a.row_bytes, w, fresh, cnt);
-        if (fresh) {
-          int32_t thr = a.nbr_d[(int64_t)w * a.k_pad + a.k - 1];
-          if (d < thr) emit_proposal(a, w, d, src);
-        }
+        stage(fresh && d < thr, w, d);
         uint64_t mf = ballot(fresh);
         upd += __popcll(mf);
         if (keep) {
@@ -152,6 +194,7 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
       }
     }
   }
+  flush();
   if (lane == 0) {
     if (a.sims) a.sims[i] = a.evals[i] + (a.b - 1) + upd;
     if (a.stats) {

@@ -30,10 +30,15 @@ SEARCH_KERNEL = "k_search<knng::ScoreI8"
 
 
 def search_kernel_hash() -> str:
+    """Hash of the int8 search kernel's sources and of the flags it is
+    compiled with (a record taken for other code or flags is stale)."""
+    from . import build as _build
     h = hashlib.sha256()
     for rel in SEARCH_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
+    flags = _build.HIP_FLAGS + _build.SOURCE_FLAGS.get("search_u8.hip", [])
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 

@@ -116,7 +116,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (one GPU holds one graph at its "
+        print("bench.py: the library runs on one GPU only (one GPU holds one graph at its "
               "real shape; sharding across GPUs is not built). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -78,11 +78,19 @@ typedef enum { KNNG_METRIC_L2 = 0, KNNG_METRIC_COSINE = 1 } knng_metric;
 
 /*
  * Parameters (Section 3 and Algorithm 2 of the paper).
- *  dim        coordinates per point, 1 .. 4096.
+ *  dim        coordinates per point: 1 .. 256 for uint8 data; for float
+ *             data 1 .. 256 (KNNG_SCORE_EXACT), .. 512 (KNNG_SCORE_BF16),
+ *             .. 1024 (KNNG_SCORE_FP8).
  *  k          list length, 1 .. 64.
  *  dtype      KNNG_U8: uint8 points, exact integer distances (int32);
  *             KNNG_F32: float32 points, float distances.
- *  score      KNNG_U8 requires KNNG_SCORE_EXACT.
+ *  score      how the search scores candidates (float data): KNNG_SCORE_EXACT
+ *             float32 rows; KNNG_SCORE_BF16 bfloat16 copies; KNNG_SCORE_FP8
+ *             E4M3 codes with a per-row scale (rows above 256 coordinates
+ *             on the FP8 matrix cores).  Reduced-precision scores keep
+ *             min(2k, 64) candidates and re-rank them by the float32
+ *             distance; every stored distance is float32.  KNNG_U8
+ *             requires KNNG_SCORE_EXACT.
  *  capacity   largest number of nodes the graph may ever hold (< 2^31).
  *  max_batch  largest batch (insert) or query count per call.
  *  speedup    iGNNS budget: B(n) = min(n, max(k, ceil(n / speedup)))

@@ -454,8 +454,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     };
 
     // A list scan whose k candidates fit one pass is decided in the group
-    // view itself ("spaced": candidate c owned by lane c * G), without
-    // moving distances to the lane view.
+    // view itself ("spaced": candidate c is owned by its group's first lane,
+    // c * G, or c in the MFMA layout), without moving distances to the lane
+    // view.
     const bool climb_spaced = G > 1 && (a.k + SLOTS - 1) / SLOTS == 1;
 
     int restarts_used = 0;          // GNNS: restarts taken

@@ -63,6 +63,24 @@ def parse():
     return ap.parse_args()
 
 
+def search_algorithmic_bytes(score: str, dim: int, k: int, points: int, evals: float,
+                             lists: float) -> float:
+    """Bytes the searches of `points` points must move: every evaluated
+    point's scoring row (int8: d; bfloat16: 2d; FP8: d codes + a 4-byte
+    scale; float32: 4d), every adjacency list read by the climb (k ids), the
+    query row and the k (id, distance) output; float graphs also read the
+    float32 rows of the kept candidates for the re-rank.  `score` is "u8"
+    for integer graphs, else the float scoring format."""
+    is_float = score != "u8"
+    v_bytes = {"u8": dim, "bf16": 2 * dim, "fp8": dim + 4, "exact": 4 * dim}[score]
+    q_bytes = 4 * dim if is_float else dim
+    keep = min(64, 2 * k) if score in ("bf16", "fp8") else k
+    total = evals * v_bytes + lists * k * 4 + points * (q_bytes + k * 8)
+    if is_float:
+        total += points * keep * 4 * dim
+    return total
+
+
 def recorded_traffic(grid_threads: int):
     """HBM bytes per search launch (int8 rows) from the committed counter
     record, or None if there is none or it was taken on a different kernel
@@ -204,23 +222,9 @@ def main():
     log(f"[bench] {K} steps: {value:.0f} inserts/s, {1000 * elapsed / K:.3f} ms/step")
 
     # ---- roofline of the search kernel (dominant) ----------------------------
-    # bytes the method reads per evaluated point: its scoring row
-    # (int8: d; bfloat16: 2d; FP8: d codes + a 4-byte scale; float32: 4d)
-    v_bytes = {"u8": w.dim, "bf16": 2 * w.dim, "fp8": w.dim + 4,
-               "exact": 4 * w.dim}["u8" if not is_float else w.score]
-    q_bytes = w.dim if not is_float else 4 * w.dim
-    keep = min(64, 2 * w.k) if is_float and w.score in ("bf16", "fp8") else w.k
     search_ms, search_launches = stage["search"]
-    evals_total = st[:, 0].sum()
-    lists_total = st[:, 1].sum()
-    # algorithmic bytes: every evaluated point's row, every adjacency list
-    # read by the climb (k ids), the query row and the k (id, distance)
-    # output; float graphs also read the float32 rows of the kept candidates
-    # for the re-rank
-    search_bytes = (evals_total * v_bytes + lists_total * w.k * 4
-                    + inserts * (q_bytes + w.k * 8))
-    if is_float:
-        search_bytes += inserts * keep * 4 * w.dim
+    search_bytes = search_algorithmic_bytes("u8" if not is_float else w.score, w.dim, w.k,
+                                            inserts, st[:, 0].sum(), st[:, 1].sum())
     search_avg_ms = search_ms / max(search_launches, 1)
     bytes_per_launch = search_bytes / max(search_launches, 1)
     achieved = bytes_per_launch / (search_avg_ms * 1e-3) / 1e9

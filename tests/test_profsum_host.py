@@ -93,3 +93,15 @@ def test_hash_covers_compile_flags(monkeypatch):
     h0 = profsum.search_kernel_hash()
     monkeypatch.setitem(build.SOURCE_FLAGS, "search_u8.hip", ["-O2"])
     assert profsum.search_kernel_hash() != h0
+
+
+def test_search_algorithmic_bytes():
+    # int8 rows of 64 bytes, k = 10: 64 B per evaluation, 40 B per list read,
+    # 64 B of query and 80 B of output per point
+    got = bench.search_algorithmic_bytes("u8", 64, 10, 256, 2_000_000.0, 150_000.0)
+    assert got == pytest.approx(2_000_000 * 64 + 150_000 * 40 + 256 * (64 + 80))
+    # float graphs add the re-rank's float32 rows of the kept candidates
+    b = bench.search_algorithmic_bytes("bf16", 128, 20, 1, 100.0, 10.0)
+    assert b == pytest.approx(100 * 256 + 10 * 80 + 512 + 160 + 40 * 512)
+    b = bench.search_algorithmic_bytes("fp8", 960, 50, 1, 1.0, 0.0)
+    assert b == pytest.approx(964 + 3840 + 400 + 64 * 3840)

@@ -33,21 +33,27 @@ class GaussianMixture:
     def dim(self) -> int:
         return int(self.centres.shape[1])
 
-    def sample(self, count: int, stream_seed: int, chunk: int = 1 << 16) -> np.ndarray:
+    def sample(self, count: int, stream_seed: int, chunk: int = 1 << 16,
+               with_labels: bool = False):
         """Draw ``count`` points from the mixture with its own stream seed.
 
         Drawing is chunked so that large streams do not need a float64 copy
         of the whole output; the chunking is part of the stream definition
-        (labels, then noise, per chunk of ``chunk`` points).
+        (labels, then noise, per chunk of ``chunk`` points).  With
+        ``with_labels`` the mixture component of every point is returned too
+        (the same stream: labels do not change the points).
         """
         rng = np.random.default_rng(stream_seed)
         d = self.dim
         out_dtype = np.uint8 if self.kind == "u8" else np.float32
         out = np.empty((count, d), dtype=out_dtype)
+        labels = np.empty(count, dtype=np.int32) if with_labels else None
         C = self.centres.shape[0]
         for lo in range(0, count, chunk):
             hi = min(count, lo + chunk)
             lab = rng.integers(0, C, size=hi - lo)
+            if labels is not None:
+                labels[lo:hi] = lab
             x = self.centres[lab] + rng.standard_normal((hi - lo, d)) * self.sigma[lab][:, None]
             if self.dim_scale is not None:
                 x = x * self.dim_scale[None, :]
@@ -55,6 +61,8 @@ class GaussianMixture:
                 out[lo:hi] = np.clip(np.rint(x), 0, 255).astype(np.uint8)
             else:
                 out[lo:hi] = x.astype(np.float32)
+        if with_labels:
+            return out, labels
         return out
 
 

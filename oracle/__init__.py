@@ -14,6 +14,9 @@ silent are listed in each function's docstring):
 
 * exact k-nn graph by brute force (Section 2.1, "naive method"; Section
   8.5.2 uses it as ground truth)            -> :func:`exact.exact_graph`
+* the same lists one row at a time, exact by branch and bound over any
+  grouping of the points, and a snapshot graph whose lists are computed on
+  first use (large initial graphs)            -> :class:`exact.LazyExactGraph`
 * improved graph nearest-neighbour search, iGNNS (Section 3: random restart
   with the expansion test, eager first-improvement step, budget stop after
   n / speedup similarities)                   -> :func:`ignns.ignns`
@@ -46,7 +49,8 @@ value in the paper and is "parity unpinned" beyond those properties.
 
 from .distance import sqdist, sqdist_many, INF_INT  # noqa: F401
 from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
-from .exact import ExactRows, exact_graph, exact_graph_loops, exact_row  # noqa: F401
+from .exact import (ExactRows, GroupedExactRows, LazyExactGraph, exact_graph,  # noqa: F401
+                    exact_graph_loops, exact_row)
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
 from .gnns import gnns  # noqa: F401

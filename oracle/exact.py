@@ -181,3 +181,97 @@ class ExactRows:
         if not cd[-1] > cd[kk - 1]:
             return exact_row(self.X, 0, kk, q=q, exclude=exclude)
         return [(int(cd[j]), int(cand[j])) for j in range(kk)]
+
+
+class GroupedExactRows:
+    """Exact lists of single points against a fixed point set by branch and
+    bound over a partition of the set, by the definition above (first k of
+    (d(q, v), v) sorted lexicographically; d in the direct float64 form, or
+    exact integers for uint8 points).
+
+    ``groups`` is any partition of the rows (an int array of group labels);
+    it only decides how fast a row is found, never which row: every group
+    has a centre c (its float64 mean) and a radius r = max |x - c| over its
+    members, so every member is at Euclidean distance at least |q - c| - r
+    from q (triangle inequality).  Groups are brute-forced in increasing
+    order of that bound, and the search stops only when the next bound,
+    squared and shrunk by a rounding margin, is strictly above the current
+    k-th distance: no point of the remaining groups can then be closer or
+    tie it.
+    """
+
+    _MARGIN = 1e-9    # relative slack covering float64 rounding of the bound
+
+    def __init__(self, X: np.ndarray, k: int, groups: np.ndarray):
+        self.X = X
+        self.k = k
+        n = X.shape[0]
+        groups = np.asarray(groups)
+        if groups.shape != (n,):
+            raise ValueError("groups must label every row")
+        order = np.argsort(groups, kind="stable")
+        labels, starts = np.unique(groups[order], return_index=True)
+        ends = np.append(starts[1:], n)
+        self.members = [order[s:e] for s, e in zip(starts, ends)]
+        Xf = X.astype(np.float64)
+        self.centres = np.stack([Xf[m].mean(axis=0) for m in self.members])
+        self.radius = np.array([np.sqrt(sqdist_many(c, Xf[m]).max())
+                                for c, m in zip(self.centres, self.members)])
+
+    def row(self, q: np.ndarray, exclude: int | None = None):
+        n = self.X.shape[0]
+        kk = min(self.k, n - (1 if exclude is not None else 0))
+        if kk <= 0:
+            return []
+        dc = np.sqrt(sqdist_many(q.astype(np.float64), self.centres))
+        lb = np.maximum(dc - self.radius, 0.0)
+        best_d = np.empty(0)
+        best_v = np.empty(0, dtype=np.int64)
+        for gi in np.argsort(lb, kind="stable"):
+            if len(best_d) == kk:
+                kth = best_d[-1]
+                if lb[gi] * lb[gi] * (1.0 - self._MARGIN) > kth:
+                    break
+            m = self.members[gi]
+            if exclude is not None:
+                m = m[m != exclude]
+            if len(m) == 0:
+                continue
+            d = sqdist_many(q, self.X[m])
+            cd = np.concatenate([best_d, d])
+            cv = np.concatenate([best_v, m.astype(np.int64)])
+            o = np.lexsort((cv, cd))[:kk]                 # by distance, then id
+            best_d, best_v = cd[o], cv[o]
+        return [(best_d[j].item(), int(best_v[j])) for j in range(len(best_d))]
+
+
+class LazyExactGraph:
+    """The exact k-nn graph of a point set (Section 8.5.2's ground truth, the
+    initial graph of the online method) whose lists are computed on first
+    use and kept: it answers what the online insertion reads from a snapshot
+    -- points, node count and the stored lists of the nodes it visits --
+    without building every list.  Lists come from :class:`GroupedExactRows`
+    (exact for any grouping)."""
+
+    def __init__(self, X: np.ndarray, k: int, groups: np.ndarray):
+        self.X = X
+        self.k = k
+        self._rows = GroupedExactRows(X, k, groups)
+        self._cache: dict[int, list] = {}
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+    def neighbour_pairs(self, u: int) -> list[tuple]:
+        got = self._cache.get(u)
+        if got is None:
+            got = self._rows.row(self.X[u], exclude=u)
+            self._cache[u] = got
+        return list(got)
+
+    def neighbours(self, u: int) -> list[int]:
+        return [v for _, v in self.neighbour_pairs(u)]
+
+    def cached(self) -> int:
+        return len(self._cache)

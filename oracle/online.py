@@ -96,8 +96,11 @@ def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int):
     return props, upd
 
 
-def insert_batch(g: OracleGraph, Y: np.ndarray, p: Params, record: bool = False) -> BatchResult:
-    """Insert the points Y (one batch) into g; g itself is not modified."""
+def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False):
+    """Steps (i)-(iii) of a batch on the snapshot g: returns (search results,
+    final lists F_i, proposals in emission order, update evaluations, sims).
+    Reads from g only its points, node count and stored lists, so g may be
+    any snapshot that provides them (e.g. :class:`exact.LazyExactGraph`)."""
     n = g.n
     b = Y.shape[0]
     k = p.k
@@ -119,23 +122,38 @@ def insert_batch(g: OracleGraph, Y: np.ndarray, p: Params, record: bool = False)
         props, upd = _update_proposals(g, Y[i], n + i, search[i].pairs, p.depth)
         proposals.extend(props)
         update_evals.append(upd)
-    # (iv) merge
+    sims = [search[i].evals + (b - 1) + update_evals[i] for i in range(b)]
+    return search, final_lists, proposals, update_evals, sims
+
+
+def merge_proposals(g, proposals: list, k: int) -> dict:
+    """Step (iv) for the targets that received proposals: {u: the first k of
+    u's stored list together with its proposals, by (distance, id)}."""
     by_target: dict[int, list] = {}
     for u, d, src in proposals:
         by_target.setdefault(u, []).append((d, src))
+    return {u: sorted(g.neighbour_pairs(u) + props)[:k] for u, props in by_target.items()}
+
+
+def insert_batch(g: OracleGraph, Y: np.ndarray, p: Params, record: bool = False) -> BatchResult:
+    """Insert the points Y (one batch) into g; g itself is not modified."""
+    n = g.n
+    b = Y.shape[0]
+    k = p.k
+    search, final_lists, proposals, update_evals, sims = search_and_propose(g, Y, p, record)
+    # (iv) merge
+    merged = merge_proposals(g, proposals, k)
     ids_new, dist_new = empty_lists(n + b, k, g.X.dtype)
     ids_new[:n] = g.ids
     dist_new[:n] = g.dist
-    for u, props in by_target.items():
-        merged = sorted(g.neighbour_pairs(u) + props)[:k]
+    for u, pairs in merged.items():
         ids_new[u, :] = -1
         dist_new[u, :] = _pad_value(dist_new)
-        write_list(ids_new, dist_new, u, merged)
+        write_list(ids_new, dist_new, u, pairs)
     for i in range(b):
         write_list(ids_new, dist_new, n + i, final_lists[i])
     # (v)
     X_new = np.concatenate([g.X, Y], axis=0)
-    sims = [search[i].evals + (b - 1) + update_evals[i] for i in range(b)]
     return BatchResult(graph=OracleGraph(X_new, ids_new, dist_new, k), search=search,
                        final_lists=final_lists, proposals=proposals,
                        update_evals=update_evals, sims=sims)

@@ -6,5 +6,5 @@ of the k-nn graph method's arithmetic, so that the oracle and the GPU path can
 both draw identical inputs without sharing any of the method's code.
 """
 
-from .gmm import GaussianMixture, u8_mixture, float_mixture  # noqa: F401
+from .gmm import GaussianMixture, u8_mixture, float_mixture, subspace_mixture  # noqa: F401
 from .workloads import WORKLOADS, Workload, get_workload  # noqa: F401

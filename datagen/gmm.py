@@ -22,12 +22,20 @@ class GaussianMixture:
     ``kind`` is ``"u8"`` (round half-to-even, clip to [0, 255], uint8) or
     ``"f32"`` (float32).  ``dim_scale`` (optional, shape [d]) multiplies every
     coordinate after sampling; it models heavy-tailed per-dimension scales.
+
+    ``basis`` (optional, shape [C, d, r], orthonormal columns) makes every
+    component r-dimensional: a point of component c is
+    ``centres[c] + sigma[c] * basis[c] @ z`` with z ~ N(0, I_r), plus
+    isotropic noise of standard deviation ``noise * sigma[c]`` in all d
+    coordinates.  Without it a component is isotropic in all d coordinates.
     """
 
     centres: np.ndarray          # [C, d] float64
     sigma: np.ndarray            # [C] float64
     kind: str                    # "u8" | "f32"
     dim_scale: np.ndarray | None = None
+    basis: np.ndarray | None = None      # [C, d, r]
+    noise: float = 0.0
 
     @property
     def dim(self) -> int:
@@ -54,7 +62,15 @@ class GaussianMixture:
             lab = rng.integers(0, C, size=hi - lo)
             if labels is not None:
                 labels[lo:hi] = lab
-            x = self.centres[lab] + rng.standard_normal((hi - lo, d)) * self.sigma[lab][:, None]
+            sig = self.sigma[lab]
+            if self.basis is None:
+                x = self.centres[lab] + rng.standard_normal((hi - lo, d)) * sig[:, None]
+            else:
+                r = self.basis.shape[2]
+                z = rng.standard_normal((hi - lo, r))
+                x = self.centres[lab] + rng.standard_normal((hi - lo, d)) * (self.noise * sig)[:, None]
+                for j in range(r):
+                    x += (sig * z[:, j])[:, None] * self.basis[lab, :, j]
             if self.dim_scale is not None:
                 x = x * self.dim_scale[None, :]
             if self.kind == "u8":
@@ -89,3 +105,17 @@ def float_mixture(seed: int, n_clusters: int, dim: int, sigma_lo: float = 0.05,
     if lognormal_dim_scale is not None:
         scale = rng.lognormal(0.0, lognormal_dim_scale, size=dim)
     return GaussianMixture(centres=centres, sigma=sig, kind="f32", dim_scale=scale)
+
+
+def subspace_mixture(seed: int, n_clusters: int, dim: int, rank: int, sigma_lo: float = 0.05,
+                     sigma_hi: float = 0.3, noise: float = 0.05) -> GaussianMixture:
+    """Mixture with centres ~ N(0, 1)^dim whose components are ``rank``-dimensional
+    Gaussians (standard deviation sigma ~ U[lo, hi] along ``rank`` random
+    orthonormal directions per component) plus isotropic noise of standard
+    deviation ``noise * sigma`` in every coordinate."""
+    rng = np.random.default_rng(seed)
+    centres = rng.standard_normal((n_clusters, dim))
+    sig = rng.uniform(sigma_lo, sigma_hi, size=n_clusters)
+    g = rng.standard_normal((n_clusters, dim, rank))
+    basis, _ = np.linalg.qr(g)
+    return GaussianMixture(centres=centres, sigma=sig, kind="f32", basis=basis, noise=float(noise))

@@ -15,7 +15,7 @@ from dataclasses import dataclass, replace
 
 import numpy as np
 
-from .gmm import GaussianMixture, float_mixture, u8_mixture
+from .gmm import GaussianMixture, float_mixture, subspace_mixture, u8_mixture
 
 
 @dataclass(frozen=True)
@@ -32,6 +32,8 @@ class Workload:
     # mixture recipe
     sigma: float = 0.0         # u8: common sigma
     lognormal_dim_scale: float | None = None
+    subspace_rank: int | None = None   # components of this many dimensions
+    subspace_noise: float = 0.05       # isotropic noise, relative to sigma
     # seeds (data)
     mixture_seed: int = 0
     stream_seed: int = 1
@@ -47,6 +49,9 @@ class Workload:
     def mixture(self) -> GaussianMixture:
         if self.kind == "u8":
             return u8_mixture(self.mixture_seed, self.n_clusters, self.dim, self.sigma)
+        if self.subspace_rank is not None:
+            return subspace_mixture(self.mixture_seed, self.n_clusters, self.dim,
+                                    self.subspace_rank, noise=self.subspace_noise)
         return float_mixture(self.mixture_seed, self.n_clusters, self.dim,
                              lognormal_dim_scale=self.lognormal_dim_scale)
 
@@ -103,10 +108,22 @@ WORKLOADS: dict[str, Workload] = {
         n_insert=50_000, batch=1024, n_query=0, n_clusters=1000,
         mixture_seed=31, stream_seed=32, query_seed=33,
         speedup=5, expansion_num=3, expansion_den=2, depth=2, score="bf16"),
-    # Serving: graph grows 1,000,000 -> 2,000,000, d=96 float32, 2,000 clusters, k=10.
+    # Serving: graph grows 1,000,000 -> 2,000,000, d=96 float32, 2,000
+    # components, k=10.  Each component is a 3-dimensional Gaussian (the
+    # paper's synthetic data is a Gaussian mixture in R^3) along random
+    # orthonormal directions of R^96 (sigma ~ U[0.05, 0.3]), plus isotropic
+    # noise of 0.05 sigma in all 96 coordinates; centres ~ N(0, 1)^96.
     "serve-f32-d96-1m-2m": Workload(
         name="serve-f32-d96-1m-2m", kind="f32", dim=96, k=10, n_initial=1_000_000,
-        n_insert=1_000_000, batch=4096, n_query=0, n_clusters=2000,
+        n_insert=1_000_000, batch=16384, n_query=0, n_clusters=2000,
+        mixture_seed=41, stream_seed=42, query_seed=43, subspace_rank=3,
+        speedup=10, expansion_num=3, expansion_den=2, depth=3, score="bf16"),
+    # The same sizes with isotropic 96-dimensional components (sigma ~ U[0.05,
+    # 0.3] in every coordinate): kept for the measurements that show why the
+    # serving workload uses low-dimensional components.
+    "serve-f32-d96-1m-2m-iso": Workload(
+        name="serve-f32-d96-1m-2m-iso", kind="f32", dim=96, k=10, n_initial=1_000_000,
+        n_insert=1_000_000, batch=16384, n_query=0, n_clusters=2000,
         mixture_seed=41, stream_seed=42, query_seed=43,
         speedup=10, expansion_num=3, expansion_den=2, depth=2, score="bf16"),
     # 500,000 initial float32 points, d=960, 500 clusters, heavy-tailed

@@ -171,7 +171,9 @@ knng_status knng_load(const knng_params* params, const void* x_dev, int64_t n,
  *  list_reads_dev [m] int32 out (adjacency lists read by the climb), or NULL.
  *  trace_dev  [m][trace_stride] int32 out: evaluated ids in evaluation
  *             order, -1 after the last; or NULL.  trace_stride >= B(n).
- * Read-only with respect to the graph.  m <= max_batch.
+ * Read-only with respect to the graph.  Any m >= 0 (below 2^31); with the
+ * cosine metric the call's queries are normalized into the workspace, which
+ * holds 2 * max_batch of them (KNNG_ECAPACITY beyond).
  */
 knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m,
                         const uint64_t* keys_dev, int32_t* ids_dev, void* d_dev,
@@ -220,9 +222,11 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
                               int32_t* stats_dev, hipStream_t stream);
 
 /*
- * Read-only k-nn query of m points on the current graph: iGNNS with the
- * keys 2^62 + s, where s counts every query this handle has answered
- * before (the first query of a handle has s = 0).
+ * Read-only k-nn query of m points on the current graph (the k-nn search
+ * problem of Section 2.2, answered with the iGNNS search of Section 3):
+ * iGNNS with the keys 2^62 + s, where s counts every query this handle has
+ * answered before (the first query of a handle has s = 0).  Any m >= 0
+ * (below 2^31; cosine metric: at most 2 * max_batch per call).
  *  ids_dev [m][k] int32, d_dev [m][k] int32/float, evals_dev and
  *  list_reads_dev [m] int32 (as for knng_search) or NULL.
  */
@@ -237,16 +241,19 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m,
  * knng_insert_batch(x) on S, with bit-identical results (the query keys are
  * the next m query-sequence keys; the insert keys are the new ids), but the
  * searches of both run in one launch.  Either part may be empty (b = 0 or
- * m = 0); b <= max_batch, n + b <= capacity.
+ * m = 0); b <= max_batch, n + b <= capacity (cosine metric: b + m <=
+ * 2 * max_batch).
  *  x_dev          [b][dim] insert points, device (may be NULL if b = 0).
  *  q_dev          [m][dim] query points; q_ids_dev [m][k] int32 out,
- *                 q_d_dev [m][k] int32 / float out, q_evals_dev [m] int32 out
- *                 or NULL.
+ *                 q_d_dev [m][k] int32 / float out, q_evals_dev and
+ *                 q_list_reads_dev [m] int32 out (as for knng_search) or NULL.
  *  first_id_host  out: n, or NULL.   sims_dev [b] int32 out, or NULL.
+ *  stats_dev      [b][3] int32 out (as for knng_insert_batch), or NULL.
  */
 knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* q_dev,
                        int64_t m, int32_t* q_ids_dev, void* q_d_dev, int32_t* q_evals_dev,
-                       int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream);
+                       int32_t* q_list_reads_dev, int64_t* first_id_host, int32_t* sims_dev,
+                       int32_t* stats_dev, hipStream_t stream);
 
 /*
  * Balanced k-medoids partitioning of the current graph's nodes into p
@@ -326,6 +333,11 @@ knng_status knng_timing_read(knng_graph* g, double* ms_host, int64_t* launches_h
 
 /* Number of nodes (counting every insert already enqueued). */
 int64_t knng_size(const knng_graph* g);
+
+/* The search budget B(n) = min(n, max(k, ceil(n / speedup))) for a graph
+ * of n nodes (Section 3: n / speedup similarities per search); n < 0 means
+ * the graph's current size.  -1 for a NULL handle. */
+int64_t knng_budget(const knng_graph* g, int64_t n);
 
 /* Number of queries answered by knng_query so far (the next query's s). */
 int64_t knng_query_count(const knng_graph* g);

@@ -56,4 +56,5 @@ from .ignns import ignns, SearchResult  # noqa: F401
 from .gnns import gnns  # noqa: F401
 from . import cosine, partition, quantize  # noqa: F401
 from .online import (insert_batch, insert_sequential_literal, insert_stream, query,  # noqa: F401
+                     merge_proposals, point_search_and_proposals, search_and_propose,
                      BatchResult, QUERY_KEY_BASE)

@@ -96,6 +96,15 @@ def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int):
     return props, upd
 
 
+def point_search_and_proposals(g, Y: np.ndarray, i: int, p: Params, record: bool = False):
+    """Steps (i) and (iii) for batch point i of Y on the snapshot g (key
+    n + i): (search result, proposals, update evaluations).  The batch's
+    points are independent in these steps."""
+    r = ignns(g, Y[i], key=g.n + i, p=p, record=record)
+    props, upd = _update_proposals(g, Y[i], g.n + i, r.pairs, p.depth)
+    return r, props, upd
+
+
 def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False):
     """Steps (i)-(iii) of a batch on the snapshot g: returns (search results,
     final lists F_i, proposals in emission order, update evaluations, sims).
@@ -104,8 +113,10 @@ def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False):
     n = g.n
     b = Y.shape[0]
     k = p.k
-    # (i) search on the snapshot
-    search = [ignns(g, Y[i], key=n + i, p=p, record=record) for i in range(b)]
+    # (i) search on the snapshot, and (iii) update proposals against the
+    # snapshot lists, per batch point
+    per_point = [point_search_and_proposals(g, Y, i, p, record) for i in range(b)]
+    search = [r for r, _, _ in per_point]
     # (ii) batch peers
     final_lists = []
     for i in range(b):
@@ -115,11 +126,9 @@ def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False):
                 cand.append((sqdist(Y[i], Y[j]), n + j))
         cand.sort()
         final_lists.append(cand[:k])
-    # (iii) update proposals against the snapshot lists
     proposals = []
     update_evals = []
-    for i in range(b):
-        props, upd = _update_proposals(g, Y[i], n + i, search[i].pairs, p.depth)
+    for _, props, upd in per_point:
         proposals.extend(props)
         update_evals.append(upd)
     sims = [search[i].evals + (b - 1) + update_evals[i] for i in range(b)]

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "KNNG_OK", -1: "KNNG_EINVAL", -2: "KNNG_ECAPACITY", -3: "KNNG
 EXPORTED = [
     "knng_storage_bytes", "knng_workspace_bytes", "knng_build_exact", "knng_load",
     "knng_search", "knng_insert_batch", "knng_query", "knng_get_lists", "knng_get_points",
-    "knng_size", "knng_query_count", "knng_last_error", "knng_destroy",
+    "knng_size", "knng_budget", "knng_query_count", "knng_last_error", "knng_destroy",
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
     "knng_epoch", "knng_search_gnns", "knng_partition_scratch_bytes", "knng_partition",
     "knng_search_partitioned_scratch_bytes", "knng_search_partitioned",
@@ -87,6 +87,8 @@ def _load() -> ctypes.CDLL:
     lib.knng_get_points.restype = ctypes.c_int
     lib.knng_size.argtypes = [vp]
     lib.knng_size.restype = i64
+    lib.knng_budget.argtypes = [vp, i64]
+    lib.knng_budget.restype = i64
     lib.knng_query_count.argtypes = [vp]
     lib.knng_query_count.restype = i64
     lib.knng_last_error.argtypes = []
@@ -101,7 +103,7 @@ def _load() -> ctypes.CDLL:
     lib.knng_row_bytes.restype = ctypes.c_int32
     lib.knng_get_rows.argtypes = [vp, i64, i64, vp, vp, vp]
     lib.knng_get_rows.restype = ctypes.c_int
-    lib.knng_epoch.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, P(i64), vp, vp]
+    lib.knng_epoch.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, P(i64), vp, vp, vp]
     lib.knng_epoch.restype = ctypes.c_int
     lib.knng_search_gnns.argtypes = [vp, vp, i64, vp, ctypes.c_int32, vp, vp, vp, vp, i64, vp]
     lib.knng_search_gnns.restype = ctypes.c_int

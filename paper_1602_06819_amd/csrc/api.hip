@@ -892,7 +892,8 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
 
 knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* q_dev,
                        int64_t m, int32_t* q_ids_dev, void* q_d_dev, int32_t* q_evals_dev,
-                       int64_t* first_id_host, int32_t* sims_dev, hipStream_t stream) {
+                       int32_t* q_list_reads_dev, int64_t* first_id_host, int32_t* sims_dev,
+                       int32_t* stats_dev, hipStream_t stream) {
   if (!g) return fail(KNNG_EINVAL, "graph is NULL");
   knng_status s;
   if (b < 0 || m < 0 || m >= ((int64_t)1 << 31))
@@ -916,11 +917,12 @@ knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* 
   // one search launch: the batch's points (keys = ids) and the queries
   // (keys 2^62 + query count), both on the snapshot of n nodes
   SearchRows qr = query_rows(q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount,
-                             q_ids_dev, q_d_dev, g->S.k, q_evals_dev, nullptr, nullptr, 0);
+                             q_ids_dev, q_d_dev, g->S.k, q_evals_dev, q_list_reads_dev,
+                             nullptr, 0);
   SearchRows ir = insert_rows(g, x_dev, b);
   if ((s = run_search(g, ir, &qr, KNNG_STAGE_SEARCH, stream)) != KNNG_OK) return s;
   g->qcount += m;
-  if (b > 0 && (s = insert_after_search(g, b, sims_dev, nullptr, stream)) != KNNG_OK) return s;
+  if (b > 0 && (s = insert_after_search(g, b, sims_dev, stats_dev, stream)) != KNNG_OK) return s;
   return ok();
 }
 
@@ -1146,6 +1148,11 @@ knng_status knng_timing_read(knng_graph* g, double* ms_host, int64_t* launches_h
 }
 
 int64_t knng_size(const knng_graph* g) { return g ? g->n : -1; }
+
+int64_t knng_budget(const knng_graph* g, int64_t n) {
+  if (!g) return -1;
+  return budget(n < 0 ? g->n : n, g->S.k, g->p.speedup);
+}
 
 int64_t knng_query_count(const knng_graph* g) { return g ? g->qcount : -1; }
 

@@ -170,11 +170,13 @@ class KnnGraph:
         return first.value, out
 
     def epoch(self, x: torch.Tensor | None, q: torch.Tensor | None, sims: bool = False,
-              stream=None):
+              stats: bool = False, stream=None):
         """One serving epoch on the current snapshot: queries q and the insert
         batch x searched in one launch, then the batch's update.  Returns
         (first id, sims or None, query ids, query d, query evals); the query
-        outputs are None when q is None."""
+        outputs are None when q is None.  With ``stats`` two more items
+        follow: the inserts' [b, 3] stats (as :meth:`insert`) and the
+        queries' list reads [m] (None where empty)."""
         b = 0 if x is None else x.shape[0]
         m = 0 if q is None else q.shape[0]
         if b:
@@ -185,10 +187,14 @@ class KnnGraph:
         qd = torch.empty((m, self.cfg.k), dtype=self._dist_dtype(), device=self.device) if m else None
         qe = torch.empty(m, dtype=torch.int32, device=self.device) if m else None
         out = torch.empty(b, dtype=torch.int32, device=self.device) if (sims and b) else None
+        st = torch.empty((b, 3), dtype=torch.int32, device=self.device) if (stats and b) else None
+        qlr = torch.empty(m, dtype=torch.int32, device=self.device) if (stats and m) else None
         first = ctypes.c_int64(0)
         check(_lib.lib.knng_epoch(self._h, _ptr(x) if b else None, b, _ptr(q) if m else None, m,
-                                  _ptr(qi), _ptr(qd), _ptr(qe), ctypes.byref(first), _ptr(out),
-                                  _stream(stream)))
+                                  _ptr(qi), _ptr(qd), _ptr(qe), _ptr(qlr), ctypes.byref(first),
+                                  _ptr(out), _ptr(st), _stream(stream)))
+        if stats:
+            return first.value, out, qi, qd, qe, st, qlr
         return first.value, out, qi, qd, qe
 
     def search(self, q: torch.Tensor, keys: torch.Tensor, trace: bool = False,
@@ -318,6 +324,5 @@ class KnnGraph:
         return rows, scale
 
     def budget(self, n: int | None = None) -> int:
-        n = self.n if n is None else n
-        b = -(-n // self.cfg.speedup)
-        return min(n, max(self.cfg.k, b))
+        """The search budget B(n) of the library (current size if n is None)."""
+        return int(_lib.lib.knng_budget(self._h, -1 if n is None else n))

@@ -24,20 +24,24 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SEARCH_SOURCES = ["csrc/search.h", "csrc/search_u8.hip", "csrc/device.h", "csrc/common.h",
-                  "csrc/internal.h"]
-SEARCH_KERNEL = "k_search<knng::ScoreI8"
+SEARCH_SOURCES = ["csrc/search.h", "csrc/device.h", "csrc/common.h", "csrc/internal.h"]
+# the instantiation unit and the kernel-name prefix of each scoring format
+SEARCH_UNITS = {"i8": ("search_u8.hip", "k_search<knng::ScoreI8"),
+                "bf16": ("search_bf16.hip", "k_search<knng::ScoreBF16")}
+SEARCH_KERNEL = SEARCH_UNITS["i8"][1]
 
 
-def search_kernel_hash() -> str:
-    """Hash of the int8 search kernel's sources and of the flags it is
-    compiled with (a record taken for other code or flags is stale)."""
+def search_kernel_hash(fmt: str = "i8") -> str:
+    """Hash of the search kernel's sources for one scoring format and of the
+    flags it is compiled with (a record taken for other code or flags is
+    stale)."""
     from . import build as _build
+    unit = SEARCH_UNITS[fmt][0]
     h = hashlib.sha256()
-    for rel in SEARCH_SOURCES:
+    for rel in SEARCH_SOURCES[:1] + ["csrc/" + unit] + SEARCH_SOURCES[1:]:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
-    flags = _build.HIP_FLAGS + _build.SOURCE_FLAGS.get("search_u8.hip", [])
+    flags = _build.HIP_FLAGS + _build.SOURCE_FLAGS.get(unit, [])
     h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 

@@ -620,7 +620,8 @@ def bench_serving(args, w) -> dict:
     achieved = bytes_per_launch / (search_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": recorded_serving_traffic(w.name, K, step_ins, ep_ins, ep_q),
+                "traffic": recorded_serving_traffic(
+                    w.name, serving_run_shape(w, K, step_ins, ep_ins, ep_q)),
                 "kernel": f"k_search ({w.score} rows)",
                 "avg_launch_ms": search_avg_ms,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
@@ -762,7 +763,14 @@ def calibration_copy(mib: int, dev) -> None:
     del src, dst
 
 
-def recorded_serving_traffic(workload: str, steps: int, step_ins: int, ep_ins: int, ep_q: int):
+def serving_run_shape(w, steps: int, step_ins: int, ep_ins: int, ep_q: int) -> dict:
+    """What a counter record of the serving run must match to be reported."""
+    return {"steps": steps, "step_inserts": step_ins, "epoch_inserts": ep_ins,
+            "epoch_queries": ep_q, "speedup": w.speedup,
+            "expansion": f"{w.expansion_num}/{w.expansion_den}", "depth": w.depth}
+
+
+def recorded_serving_traffic(workload: str, run_shape: dict):
     """HBM bytes per search launch of the serving run from the committed
     counter record, or None if there is none, it was taken on another
     kernel source or flags, or on another run shape."""
@@ -774,8 +782,7 @@ def recorded_serving_traffic(workload: str, steps: int, step_ins: int, ep_ins: i
         rec = json.load(f)
     if rec.get("source_hash") != profsum.search_kernel_hash("bf16"):
         return None
-    if rec.get("run") != {"steps": steps, "step_inserts": step_ins, "epoch_inserts": ep_ins,
-                          "epoch_queries": ep_q}:
+    if rec.get("run") != run_shape:
         return None
     return rec.get("bytes_per_dispatch")
 

@@ -295,6 +295,27 @@ knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
                                     void* scratch_dev, size_t scratch_bytes, int32_t* ids_dev,
                                     void* d_dev, int32_t* evals_dev, hipStream_t stream);
 
+/*
+ * knng_search_partitioned without the caller's scratch, for callers that
+ * cannot allocate device memory per call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  The per-call
+ * scratch (knng_search_partitioned_scratch_bytes(g, m, p) bytes) comes from
+ * a static device array of 32 MiB that the library holds on every GPU it
+ * runs on until the process ends; calls needing more return KNNG_ECAPACITY
+ * (with k <= 16 and p = 8 that is about 31,000 queries per call).  Nothing
+ * is allocated: no hipMalloc, hipFree or allocating library routine.  The
+ * calling thread's current device must be the graph's device.  Every call
+ * on one GPU shares that GPU's array, so calls that overlap on one GPU
+ * (other streams, other threads, other handles) race; calls on one stream
+ * are ordered.  Every byte of the scratch a call reads it has written
+ * first, so the previous call's contents never reach a result.  Arguments
+ * and results as knng_search_partitioned.
+ */
+knng_status knng_search_partitioned_noalloc(knng_graph* g, const void* q_dev, int64_t m,
+                                            const uint64_t* keys_dev, const int32_t* part_dev,
+                                            int32_t p, int32_t* ids_dev, void* d_dev,
+                                            int32_t* evals_dev, hipStream_t stream);
+
 /* Copy lists of nodes [first, first + count) out: ids_dev [count][k] int32,
  * d_dev [count][k] int32/float (either may be NULL). */
 knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count,

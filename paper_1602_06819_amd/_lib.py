@@ -28,6 +28,7 @@ EXPORTED = [
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
     "knng_epoch", "knng_search_gnns", "knng_partition_scratch_bytes", "knng_partition",
     "knng_search_partitioned_scratch_bytes", "knng_search_partitioned",
+    "knng_search_partitioned_noalloc",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -118,6 +119,9 @@ def _load() -> ctypes.CDLL:
     lib.knng_search_partitioned.argtypes = [vp, vp, i64, vp, vp, ctypes.c_int32, vp,
                                             ctypes.c_size_t, vp, vp, vp, vp]
     lib.knng_search_partitioned.restype = ctypes.c_int
+    lib.knng_search_partitioned_noalloc.argtypes = [vp, vp, i64, vp, vp, ctypes.c_int32, vp, vp,
+                                                    vp, vp]
+    lib.knng_search_partitioned_noalloc.restype = ctypes.c_int
     return lib
 
 

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -716,6 +717,111 @@ SearchPartScratch search_part_scratch(int64_t m, int p, int k_pad) {
   return P;
 }
 
+// Argument checks shared by the partitioned searches (m == 0 is a no-op).
+knng_status check_partitioned(knng_graph* g, const void* q_dev, int64_t m,
+                              const uint64_t* keys_dev, const int32_t* part_dev, int32_t p,
+                              int32_t* ids_dev, void* d_dev) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  if (m == 0) return ok();
+  if (m < 0 || m * (int64_t)p >= ((int64_t)1 << 31))
+    return fail(KNNG_EINVAL, "m * p must be below 2^31");
+  if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
+  if (g->S.is_float && g->S.format != ROW_F32)
+    return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs and float graphs "
+                             "with float32 scoring");
+  if (g->S.cosine) return fail(KNNG_EINVAL, "partitioned search does not take the cosine metric");
+  knng_status s;
+  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(part_dev, "part_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
+  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
+  return KNNG_OK;
+}
+
+// The partitioned search proper, with its per-call scratch at `sc` (sized
+// by search_part_scratch; every byte of it is written before it is read, so
+// it needs no clearing).
+knng_status search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
+                               const uint64_t* keys_dev, const int32_t* part_dev, int32_t p,
+                               char* sc, int32_t* ids_dev, void* d_dev, int32_t* evals_dev,
+                               hipStream_t stream) {
+  const SearchPartScratch P = search_part_scratch(m, p, g->S.k_pad);
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  int32_t* rid = reinterpret_cast<int32_t*>(sc + P.off_ids);
+  int32_t* rd = reinterpret_cast<int32_t*>(sc + P.off_d);
+  int32_t* rev = reinterpret_cast<int32_t*>(sc + P.off_evals);
+  int32_t* counts = reinterpret_cast<int32_t*>(sc + P.off_counts);
+  int32_t* budgets = reinterpret_cast<int32_t*>(sc + P.off_budgets);
+  KNNG_TRY(launch_part_budgets(part_dev, (int32_t)g->n, p, S.k, g->p.speedup, counts, budgets,
+                               stream),
+           "budget launch");
+  SearchArgs a{};
+  a.format = S.format;
+  a.vec = at<char>(g->st, S.off_vec);
+  a.row_bytes = S.row_bytes;
+  a.nbr_ids = at<int32_t>(g->st, S.off_ids);
+  a.k = S.k;
+  a.k_pad = S.k_pad;
+  a.keep = S.k;
+  a.n = (int32_t)g->n;
+  a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
+  a.m_mod = modulus_for(g->n);
+  a.e_num = g->p.expansion_num;
+  a.e_den = g->p.expansion_den;
+  a.seed = g->p.seed;
+  a.dim = S.dim;
+  a.rows[0] = query_rows(q_dev, m * p, keys_dev, 0, rid, rd, S.k_pad, rev, nullptr, nullptr, 0);
+  a.pad_bits = (uint32_t)S.pad;
+  if (search_sets_global(g->n)) {
+    a.gvis = at<uint32_t>(g->ws, W.off_sets);
+    a.gvis_slots = W.set_slots;
+  }
+  if (S.is_float) {
+    a.master = at<float>(g->st, S.off_master);
+    a.master_stride = S.mstride;
+    a.master_chunks = S.mstride / 4;
+  }
+  a.node_part = part_dev;
+  a.nparts = p;
+  a.part_budget = budgets;
+  {
+    Timed t(g, KNNG_STAGE_QUERY, stream);
+    KNNG_TRY(launch_search_part(a, stream), "search launch");
+    KNNG_TRY(launch_merge_partitions(rid, rd, rev, S.k_pad, (int32_t)m, p, S.k, ids_dev,
+                                     (int32_t*)d_dev, S.k, evals_dev, S.pad, stream),
+             "merge launch");
+  }
+  return ok();
+}
+
+// ---- static scratch of knng_search_partitioned_noalloc ------------------------------
+// One array per GPU, alive until the process ends.  In host code the name
+// `scratch` only stands for the symbol; its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+knng_status noalloc_scratch(char** out) {
+  int dev_id = -1;
+  KNNG_TRY(hipGetDevice(&dev_id), "hipGetDevice");
+  if (dev_id < 0 || dev_id >= MAX_DEVICES)
+    return fail(KNNG_EDEVICE, "device %d outside 0 .. %d", dev_id, MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev_id]) {
+    void* ptr = nullptr;
+    KNNG_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(KNNG_EDEVICE, "no device address for the static scratch");
+    g_scratch_ptr[dev_id] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev_id];
+  return KNNG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1040,74 +1146,32 @@ knng_status knng_search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
                                     const uint64_t* keys_dev, const int32_t* part_dev, int32_t p,
                                     void* scratch_dev, size_t scratch_bytes, int32_t* ids_dev,
                                     void* d_dev, int32_t* evals_dev, hipStream_t stream) {
-  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
-  if (m == 0) return ok();
-  if (m < 0 || m * (int64_t)p >= ((int64_t)1 << 31))
-    return fail(KNNG_EINVAL, "m * p must be below 2^31");
-  if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
-  if (g->S.is_float && g->S.format != ROW_F32)
-    return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs and float graphs "
-                             "with float32 scoring");
-  if (g->S.cosine) return fail(KNNG_EINVAL, "partitioned search does not take the cosine metric");
-  knng_status s;
-  if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
-  if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
-  if ((s = check_ptr(part_dev, "part_dev")) != KNNG_OK) return s;
+  knng_status s = check_partitioned(g, q_dev, m, keys_dev, part_dev, p, ids_dev, d_dev);
+  if (s != KNNG_OK || m == 0) return s;
   if ((s = check_ptr(scratch_dev, "scratch_dev")) != KNNG_OK) return s;
-  if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
-  if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
   if ((uintptr_t)scratch_dev % ALIGN) return fail(KNNG_EINVAL, "scratch must be 256-byte aligned");
-  const SearchPartScratch P = search_part_scratch(m, p, g->S.k_pad);
-  if (scratch_bytes < P.total)
-    return fail(KNNG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, P.total);
-  const StorageLayout& S = g->S;
-  const WorkspaceLayout& W = g->W;
-  char* sc = (char*)scratch_dev;
-  int32_t* rid = reinterpret_cast<int32_t*>(sc + P.off_ids);
-  int32_t* rd = reinterpret_cast<int32_t*>(sc + P.off_d);
-  int32_t* rev = reinterpret_cast<int32_t*>(sc + P.off_evals);
-  int32_t* counts = reinterpret_cast<int32_t*>(sc + P.off_counts);
-  int32_t* budgets = reinterpret_cast<int32_t*>(sc + P.off_budgets);
-  KNNG_TRY(launch_part_budgets(part_dev, (int32_t)g->n, p, S.k, g->p.speedup, counts, budgets,
-                               stream),
-           "budget launch");
-  SearchArgs a{};
-  a.format = S.format;
-  a.vec = at<char>(g->st, S.off_vec);
-  a.row_bytes = S.row_bytes;
-  a.nbr_ids = at<int32_t>(g->st, S.off_ids);
-  a.k = S.k;
-  a.k_pad = S.k_pad;
-  a.keep = S.k;
-  a.n = (int32_t)g->n;
-  a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
-  a.m_mod = modulus_for(g->n);
-  a.e_num = g->p.expansion_num;
-  a.e_den = g->p.expansion_den;
-  a.seed = g->p.seed;
-  a.dim = S.dim;
-  a.rows[0] = query_rows(q_dev, m * p, keys_dev, 0, rid, rd, S.k_pad, rev, nullptr, nullptr, 0);
-  a.pad_bits = (uint32_t)S.pad;
-  if (search_sets_global(g->n)) {
-    a.gvis = at<uint32_t>(g->ws, W.off_sets);
-    a.gvis_slots = W.set_slots;
-  }
-  if (S.is_float) {
-    a.master = at<float>(g->st, S.off_master);
-    a.master_stride = S.mstride;
-    a.master_chunks = S.mstride / 4;
-  }
-  a.node_part = part_dev;
-  a.nparts = p;
-  a.part_budget = budgets;
-  {
-    Timed t(g, KNNG_STAGE_QUERY, stream);
-    KNNG_TRY(launch_search_part(a, stream), "search launch");
-    KNNG_TRY(launch_merge_partitions(rid, rd, rev, S.k_pad, (int32_t)m, p, S.k, ids_dev,
-                                     (int32_t*)d_dev, S.k, evals_dev, S.pad, stream),
-             "merge launch");
-  }
-  return ok();
+  const size_t need = search_part_scratch(m, p, g->S.k_pad).total;
+  if (scratch_bytes < need)
+    return fail(KNNG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+  return search_partitioned(g, q_dev, m, keys_dev, part_dev, p, (char*)scratch_dev, ids_dev,
+                            d_dev, evals_dev, stream);
+}
+
+knng_status knng_search_partitioned_noalloc(knng_graph* g, const void* q_dev, int64_t m,
+                                            const uint64_t* keys_dev, const int32_t* part_dev,
+                                            int32_t p, int32_t* ids_dev, void* d_dev,
+                                            int32_t* evals_dev, hipStream_t stream) {
+  knng_status s = check_partitioned(g, q_dev, m, keys_dev, part_dev, p, ids_dev, d_dev);
+  if (s != KNNG_OK || m == 0) return s;
+  const size_t need = search_part_scratch(m, p, g->S.k_pad).total;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(KNNG_ECAPACITY, "m = %lld queries in %d parts need %zu bytes of scratch; the "
+                                "static scratch holds %zu (use knng_search_partitioned)",
+                (long long)m, p, need, NOALLOC_SCRATCH_BYTES);
+  char* sc = nullptr;
+  if ((s = noalloc_scratch(&sc)) != KNNG_OK) return s;
+  return search_partitioned(g, q_dev, m, keys_dev, part_dev, p, sc, ids_dev, d_dev, evals_dev,
+                            stream);
 }
 
 knng_status knng_timing_enable(knng_graph* g, int enable) {

@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--speedup", type=int, default=None, help="override the search speedup")
     ap.add_argument("--depth", type=int, default=None, help="override the update depth")
     ap.add_argument("--expansion", default=None, help="override e as num/den, e.g. 5/1")
-    ap.add_argument("--score", default=None, choices=["exact", "bf16", "fp8"],
+    ap.add_argument("--score", default=None, choices=["exact", "bf16", "bf16m", "fp8"],
                     help="override the scoring rows of a float workload")
     ap.add_argument("--step-inserts", type=int, default=50_000,
                     help="serving: inserted points admitted per step")
@@ -93,15 +93,17 @@ def parse():
 def search_algorithmic_bytes(score: str, dim: int, k: int, points: int, evals: float,
                              lists: float) -> float:
     """Bytes the searches of `points` points must move: every evaluated
-    point's scoring row (int8: d; bfloat16: 2d; FP8: d codes + a 4-byte
-    scale; float32: 4d), every adjacency list read by the climb (k ids), the
+    point's scoring row (int8: d; bfloat16: 2d, plus the 4-byte row norm
+    when scored on the matrix cores; FP8: d codes + a 4-byte scale; float32:
+    4d), every adjacency list read by the climb (k ids), the
     query row and the k (id, distance) output; float graphs also read the
     float32 rows of the kept candidates for the re-rank.  `score` is "u8"
     for integer graphs, else the float scoring format."""
     is_float = score != "u8"
-    v_bytes = {"u8": dim, "bf16": 2 * dim, "fp8": dim + 4, "exact": 4 * dim}[score]
+    v_bytes = {"u8": dim, "bf16": 2 * dim, "bf16m": 2 * dim + 4, "fp8": dim + 4,
+               "exact": 4 * dim}[score]
     q_bytes = 4 * dim if is_float else dim
-    keep = min(64, 2 * k) if score in ("bf16", "fp8") else k
+    keep = min(64, 2 * k) if score in ("bf16", "bf16m", "fp8") else k
     total = evals * v_bytes + lists * k * 4 + points * (q_bytes + k * 8)
     if is_float:
         total += points * keep * 4 * dim
@@ -342,7 +344,7 @@ def bench_batches(args, w) -> dict:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8" if not is_float else {"bf16": "bf16", "fp8": "fp8",
+        "dtype": "int8" if not is_float else {"bf16": "bf16", "bf16m": "bf16", "fp8": "fp8",
                                                "exact": "f32"}[w.score],
         "data": "synthetic",
         "config": {"workload": w.name, "n_initial": n0, "dim": w.dim, "k": w.k, "batch": b,
@@ -722,7 +724,7 @@ def bench_serving(args, w) -> dict:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16": "bf16", "fp8": "fp8", "exact": "f32"}[w.score],
+        "dtype": {"bf16": "bf16", "bf16m": "bf16", "fp8": "fp8", "exact": "f32"}[w.score],
         "data": "synthetic",
         "config": {"workload": w.name, "n_initial": n0, "n_final": n_final, "dim": w.dim,
                    "k": w.k, "step_inserts": step_ins, "epoch_max_inserts": ep_ins,

@@ -67,7 +67,12 @@ typedef enum {
   KNNG_STAGE_QUERY = 6,   /* iGNNS of knng_search / knng_query              */
   KNNG_NUM_STAGES = 7
 } knng_stage;
-typedef enum { KNNG_SCORE_EXACT = 0, KNNG_SCORE_BF16 = 1, KNNG_SCORE_FP8 = 2 } knng_score;
+typedef enum {
+  KNNG_SCORE_EXACT = 0,
+  KNNG_SCORE_BF16 = 1,
+  KNNG_SCORE_FP8 = 2,
+  KNNG_SCORE_BF16_MFMA = 3
+} knng_score;
 
 /* Dissimilarity.  KNNG_METRIC_L2: squared Euclidean distance.
  * KNNG_METRIC_COSINE (float data only): points are normalized to unit length
@@ -85,9 +90,12 @@ typedef enum { KNNG_METRIC_L2 = 0, KNNG_METRIC_COSINE = 1 } knng_metric;
  *  dtype      KNNG_U8: uint8 points, exact integer distances (int32);
  *             KNNG_F32: float32 points, float distances.
  *  score      how the search scores candidates (float data): KNNG_SCORE_EXACT
- *             float32 rows; KNNG_SCORE_BF16 bfloat16 copies; KNNG_SCORE_FP8
- *             E4M3 codes with a per-row scale (rows above 256 coordinates
- *             on the FP8 matrix cores).  Reduced-precision scores keep
+ *             float32 rows; KNNG_SCORE_BF16 bfloat16 copies (VALU dot
+ *             products); KNNG_SCORE_BF16_MFMA the same rows scored on the
+ *             bfloat16 matrix cores as |q|^2 - 2 q.x + |x|^2 (dim <= 128;
+ *             each row carries its squared norm); KNNG_SCORE_FP8 E4M3 codes
+ *             with a per-row scale (rows above 256 coordinates on the FP8
+ *             matrix cores).  Reduced-precision scores keep
  *             min(2k, 64) candidates and re-rank them by the float32
  *             distance; every stored distance is float32.  KNNG_U8
  *             requires KNNG_SCORE_EXACT.
@@ -328,9 +336,12 @@ knng_status knng_get_points(const knng_graph* g, int64_t first, int64_t count,
 
 /* Bytes of one scoring row of the search (the layout of knng_get_rows):
  * uint8 data: dim rounded up to 16 bytes of int8 (coordinate - 128);
- * float data: 2 * dim rounded up to 16 (KNNG_SCORE_BF16, bfloat16),
- * dim rounded up to 16 (KNNG_SCORE_FP8, E4M3 codes), or 4 * dim rounded up
- * to 16 (KNNG_SCORE_EXACT, the float32 rows).  -1 for a NULL handle. */
+ * float data: 2 * dim rounded up to 16 (KNNG_SCORE_BF16, bfloat16; with
+ * KNNG_SCORE_BF16_MFMA followed by a 16-byte chunk whose first 4 bytes hold
+ * the float32 squared norm of the stored bfloat16 row and the rest zeros),
+ * dim rounded up to 16 (KNNG_SCORE_FP8, E4M3 codes),
+ * or 4 * dim rounded up to 16 (KNNG_SCORE_EXACT, the float32 rows).  -1 for
+ * a NULL handle. */
 int32_t knng_row_bytes(const knng_graph* g);
 
 /* Copy the scoring rows of nodes [first, first + count) out, as stored:

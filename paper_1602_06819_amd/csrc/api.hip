@@ -166,7 +166,7 @@ bool update_sets_global(int64_t n, int64_t front_cap) {
 
 int row_format(const knng_params& p) {
   if (p.dtype == KNNG_U8) return ROW_I8;
-  if (p.score == KNNG_SCORE_BF16) return ROW_BF16;
+  if (p.score == KNNG_SCORE_BF16 || p.score == KNNG_SCORE_BF16_MFMA) return ROW_BF16;
   if (p.score == KNNG_SCORE_FP8) return ROW_FP8;
   return ROW_F32;
 }
@@ -178,7 +178,7 @@ knng_status check_params(const knng_params* p) {
   if (p->dtype != KNNG_U8 && p->dtype != KNNG_F32)
     return fail(KNNG_EINVAL, "unknown dtype %d", p->dtype);
   if (p->score != KNNG_SCORE_EXACT && p->score != KNNG_SCORE_BF16 &&
-      p->score != KNNG_SCORE_FP8)
+      p->score != KNNG_SCORE_FP8 && p->score != KNNG_SCORE_BF16_MFMA)
     return fail(KNNG_EINVAL, "unknown score %d", p->score);
   if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
     return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
@@ -189,7 +189,10 @@ knng_status check_params(const knng_params* p) {
   if (p->dtype == KNNG_U8 && p->dim > 256)
     return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
   if (p->dtype == KNNG_F32) {
-    const int lim = p->score == KNNG_SCORE_FP8 ? 1024 : p->score == KNNG_SCORE_BF16 ? 512 : 256;
+    const int lim = p->score == KNNG_SCORE_FP8            ? 1024
+                    : p->score == KNNG_SCORE_BF16         ? 512
+                    : p->score == KNNG_SCORE_BF16_MFMA    ? BF16_MFMA_DIM
+                                                          : 256;
     if (p->dim > lim)
       return fail(KNNG_EINVAL, "float data with this score supports dim <= %d (got %d)", lim,
                   p->dim);
@@ -227,10 +230,19 @@ StorageLayout storage_layout(const knng_params& p) {
   S.mstride = S.is_float ? (int)round_up(p.dim, 4) : 0;
   switch (S.format) {
     case ROW_I8: S.row_bytes = (int)round_up(p.dim, 16); break;
-    case ROW_BF16: S.row_bytes = (int)round_up(2 * (int64_t)p.dim, 16); break;
+    case ROW_BF16:
+      S.row_bytes = (int)round_up(2 * (int64_t)p.dim, 16);
+      // rows scored on the matrix cores carry their squared norm in a
+      // 16-byte chunk after the coordinates (read with the row)
+      if (p.score == KNNG_SCORE_BF16_MFMA) {
+        S.norm_off = S.row_bytes;
+        S.row_bytes += 16;
+      }
+      break;
     case ROW_FP8: S.row_bytes = (int)round_up(p.dim, 16); break;
     default: S.row_bytes = S.mstride * 4; break;
   }
+  S.coord_bytes = S.norm_off >= 0 ? S.norm_off : S.row_bytes;
   S.cap = p.capacity;
   size_t cur = 0;
   if (S.is_float) S.off_master = take(cur, (size_t)S.cap * S.mstride * 4);
@@ -238,10 +250,8 @@ StorageLayout storage_layout(const knng_params& p) {
     S.off_vec = S.off_master;
   else
     S.off_vec = take(cur, (size_t)S.cap * S.row_bytes);
-  if (S.format == ROW_FP8) {
-    S.off_scale = take(cur, (size_t)S.cap * 4);
-    S.off_qnorm = take(cur, (size_t)S.cap * 4);
-  }
+  if (S.format == ROW_FP8) S.off_scale = take(cur, (size_t)S.cap * 4);
+  if (S.format == ROW_FP8) S.off_qnorm = take(cur, (size_t)S.cap * 4);
   S.off_norms = take(cur, (size_t)S.cap * 4);
   S.off_ids = take(cur, (size_t)S.cap * S.k_pad * 4);
   S.off_dist = take(cur, (size_t)S.cap * S.k_pad * 4);
@@ -353,6 +363,8 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.row_bytes = S.row_bytes;
   a.side = S.format == ROW_FP8 ? at<uint32_t>(g->st, S.off_scale) : nullptr;
   a.side2 = S.format == ROW_FP8 ? at<uint32_t>(g->st, S.off_qnorm) : nullptr;
+  a.coord_bytes = S.coord_bytes;
+  a.side2_off = S.norm_off;
   if (S.is_float) {
     a.master = at<float>(g->st, S.off_master);
     a.master_stride = S.mstride;
@@ -468,6 +480,8 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipSt
     a.score = S.format == ROW_F32 ? nullptr : at<char>(g->st, S.off_vec) + first * S.row_bytes;
     a.scale = S.format == ROW_FP8 ? at<float>(g->st, S.off_scale) + first : nullptr;
     a.qnorm = S.format == ROW_FP8 ? at<float>(g->st, S.off_qnorm) + first : nullptr;
+    a.coord_bytes = S.coord_bytes;
+    a.norm_off = S.norm_off;
     a.m = m;
     a.dim = S.dim;
     a.stride = S.mstride;
@@ -761,6 +775,8 @@ knng_status search_partitioned(knng_graph* g, const void* q_dev, int64_t m,
   a.format = S.format;
   a.vec = at<char>(g->st, S.off_vec);
   a.row_bytes = S.row_bytes;
+  a.coord_bytes = S.coord_bytes;
+  a.side2_off = S.norm_off;
   a.nbr_ids = at<int32_t>(g->st, S.off_ids);
   a.k = S.k;
   a.k_pad = S.k_pad;

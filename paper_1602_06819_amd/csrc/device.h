@@ -12,6 +12,7 @@ namespace knng {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // ---- sums inside groups of G consecutive lanes --------------------------------
 // DPP for groups of 2 / 4 lanes (no LDS traffic), xor shuffles above.  The

@@ -29,6 +29,8 @@ enum RowFormat { ROW_I8 = 0, ROW_BF16 = 1, ROW_FP8 = 2, ROW_F32 = 3 };
 //   head   [N]             int32      first pending proposal per node (-1)
 struct StorageLayout {
   int dim = 0, k = 0, k_pad = 0, row_bytes = 0, format = ROW_I8, mstride = 0;
+  int coord_bytes = 0;   // bytes of a scoring row's coordinates (<= row_bytes)
+  int norm_off = -1;     // byte offset of a float32 row term inside the row, or -1
   bool is_float = false;
   bool cosine = false; // rows normalized to unit length (cosine metric)
   int32_t pad = 0;     // distance padding pattern
@@ -86,6 +88,9 @@ struct IngestF32Args {
   float* qnorm;        // [m] (FP8): squared norm of the quantized row, scale^2 sum v^2
   int64_t m;
   int dim, stride, row_bytes, format;
+  int coord_bytes;     // bytes of the row's coordinates
+  int norm_off;        // >= 0: the squared norm of the stored row (float32) at this byte
+                       // offset of the row, zeros after it to the end of the row
   int cosine;          // normalize rows to unit length first
   float* qout;         // if set: write only the normalized rows [m][dim] here
 };
@@ -125,8 +130,12 @@ struct SearchRows {
 struct SearchArgs {
   int format;                              // RowFormat of vec
   const void* vec; int row_bytes;          // scoring rows
+  int coord_bytes;                         // bytes of a row's coordinates (<= row_bytes)
+  int side2_off;                           // >= 0: side2 is the float32 at this byte offset
+                                           // of the row rather than in the side2 array
   const uint32_t* side;                    // per-row value: int8 norms, FP8 scales
-  const uint32_t* side2;                   // second per-row value: FP8 quantized norms
+  const uint32_t* side2;                   // second per-row value: the squared norm of the
+                                           // stored row (FP8 with its scale, or bfloat16)
   const float* master; int master_stride; int master_chunks;   // float graphs (re-rank)
   const int32_t* nbr_ids; int k, k_pad;
   int keep;              // result entries kept by the search (k, more before a re-rank)
@@ -208,6 +217,9 @@ size_t update_lds_bytes(int64_t n, int64_t front_cap, bool global_set, bool glob
 constexpr size_t LDS_LIMIT = 65536;
 // Bitsets up to this size stay in LDS; larger graphs use global bitsets.
 constexpr size_t LDS_SET_LIMIT = 40960;
+// bfloat16 rows of up to this many coordinates are scored on the matrix
+// cores and carry their squared norm inside the row.
+constexpr int BF16_MFMA_DIM = 128;
 
 // ---- launchers (each returns the hipError_t of its launch) ------------------
 hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s);

@@ -98,8 +98,20 @@ __global__ __launch_bounds__(256) void k_ingest_f32(IngestF32Args a) {
   if (lane == 0) a.norms[row] = nrm;
   if (a.format == ROW_BF16) {
     uint16_t* brow = reinterpret_cast<uint16_t*>(a.score + row * a.row_bytes);
-    for (int j = lane; j < a.row_bytes / 2; j += WAVE)
-      brow[j] = (uint16_t)(j < a.dim ? f32_to_bf16(value(j)) : 0u);
+    float qn = 0.f;                                // sum of the stored values squared
+    for (int j = lane; j < a.coord_bytes / 2; j += WAVE) {
+      const uint32_t h = j < a.dim ? f32_to_bf16(value(j)) : 0u;
+      brow[j] = (uint16_t)h;
+      const float v = bf16_lo(h);
+      qn = __builtin_fmaf(v, v, qn);
+    }
+    if (a.norm_off >= 0) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) qn += __shfl_xor(qn, off, WAVE);
+      uint32_t* tail = reinterpret_cast<uint32_t*>(a.score + row * a.row_bytes + a.norm_off);
+      const int words = (a.row_bytes - a.norm_off) / 4;
+      if (lane < words) tail[lane] = lane == 0 ? __float_as_uint(qn) : 0u;
+    }
   } else if (a.format == ROW_FP8) {
     const float scale = mx / 448.f;
     uint8_t* frow = reinterpret_cast<uint8_t*>(a.score + row * a.row_bytes);

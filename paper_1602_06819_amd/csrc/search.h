@@ -8,6 +8,8 @@
 //   ScoreF32   float32 rows: sum of (q - x)^2 in float32
 //   ScoreFP8M  FP8 rows of 257-1024 coordinates on the matrix cores:
 //              |q|^2 - 2 s q.v + s^2 sum v^2 from FP8 MFMA dot products
+//   ScoreBF16M bfloat16 rows of up to 128 coordinates on the matrix cores:
+//              |q|^2 - 2 q.x + |x|^2 from bfloat16 MFMA dot products
 //
 // Sequential semantics on a 64-lane wavefront.  Restart nodes are drawn one
 // at a time and tested, and the eager climb moves to the *first* improving
@@ -51,7 +53,7 @@ namespace knng {
 template <int G, int CPL>
 struct ScoreI8 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
   v4i q[CPL];
   int32_t qq;
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
@@ -129,7 +131,7 @@ __device__ __forceinline__ bool keep_f32(uint32_t d, uint32_t best, int num, int
 template <int G, int CPL>
 struct ScoreBF16 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
   float q[CPL][8];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 8>(a, r, qi, q);
@@ -157,7 +159,7 @@ struct ScoreBF16 {
 template <int G, int CPL>
 struct ScoreFP8 {
   static constexpr bool kSide = true;    // the row scale
-  static constexpr bool kSide2 = false, kMfma = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
   float q[CPL][16];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 16>(a, r, qi, q);
@@ -187,7 +189,7 @@ struct ScoreFP8 {
 template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
   float q[CPL][4];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
@@ -223,7 +225,7 @@ struct ScoreF32 {
 template <int CPL>
 struct ScoreFP8M {
   static_assert(CPL % 2 == 0, "an MFMA step takes two 16-byte chunks per lane");
-  static constexpr bool kSide = true, kSide2 = true, kMfma = true;
+  static constexpr bool kSide = true, kSide2 = true, kMfma = true, kBatch = false;
   static constexpr int G = 4;
   v4i qh[CPL], ql[CPL];
   float qq;                       // |q|^2
@@ -281,6 +283,95 @@ struct ScoreFP8M {
     const float dot = qs * __builtin_fmaf(al[0], 0.0625f, ah[0]);   // q . v
     const float d = __builtin_fmaf(-2.f * __uint_as_float(side), dot, qq + __uint_as_float(side2));
     return __float_as_uint(d > 0.f ? d : 0.f);
+  }
+  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+    return keep_f32(d, best, num, den);
+  }
+};
+
+// bfloat16 rows scored on the matrix cores.  One 16x16x32 bfloat16 MFMA
+// multiplies a 16-row A operand by 16 candidate rows over 32 coordinates:
+// A holds the query in two bfloat16 terms, q ~ h + l with h = bf16(q) and
+// l = bf16(q - h) (about 16 significant bits), in rows 0 and 1, and zeros
+// elsewhere, so one instruction gives both terms' dot products with 16
+// candidates.  Lane l serves candidate l % 16 (the slot) and the 8
+// coordinates 8 (l / 16) .. of each 32-coordinate block (the sub); the
+// operands pair their elements lane by lane, so the query and the rows use
+// the same chunk of coordinates per lane.  The row term |x|^2 of the stored
+// bfloat16 row is kept at ingest.  The score is |q|^2 - 2 q.x + |x|^2, i.e.
+// |q - x|^2 up to rounding (the expanded form cancels: its error is a few
+// float32 units of |q|^2 + |x|^2 rather than of the distance), clamped at
+// 0; it is valid in the candidates' sub-0 lanes 0-15.
+template <int CPL>
+struct ScoreBF16M {
+  static constexpr bool kSide = false, kSide2 = true, kMfma = true, kBatch = true;
+  static constexpr int G = 4;
+  v4i qa[CPL];                    // A operand: row 0 h, row 1 l, other rows 0
+  float qq;                       // |q|^2
+  __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
+    const int lane = lane_id();
+    const int slot = lane % 16, sub = lane / 16;
+    const float* qr = (const float*)r.qraw + (int64_t)qi * a.dim;
+    float nrm = 0.f;
+    for (int j = lane; j < a.dim; j += WAVE) nrm = __builtin_fmaf(qr[j], qr[j], nrm);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, WAVE);
+    qq = nrm;
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp) {
+      const int c0 = 8 * (sub + G * pp);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t w = 0u;
+        if (slot < 2) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const int j = c0 + 2 * e + t;
+            const float v = j < a.dim ? qr[j] : 0.f;
+            const uint32_t h = f32_to_bf16(v);
+            const uint32_t part = slot == 0 ? h : f32_to_bf16(v - bf16_lo(h));
+            w |= part << (16 * t);
+          }
+        }
+        qa[pp][e] = (int)w;
+      }
+    }
+  }
+  __device__ __forceinline__ uint32_t finish(const v4f& acc, uint32_t side2) const {
+    const float dot = acc[0] + acc[1];                                  // q . x
+    const float d = __builtin_fmaf(-2.f, dot, qq + __uint_as_float(side2));
+    return __float_as_uint(d > 0.f ? d : 0.f);
+  }
+  // one pass: the blocks' products are independent and summed afterwards
+  __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t,
+                                           uint32_t side2) const {
+    const v4f z = {0.f, 0.f, 0.f, 0.f};
+    v4f part[CPL];
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+      part[pp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, qa[pp]),
+                                                         __builtin_bit_cast(v8bf, x[pp]), z, 0,
+                                                         0, 0);
+#pragma unroll
+    for (int pp = 1; pp < CPL; ++pp) part[0] += part[pp];
+    return finish(part[0], side2);
+  }
+  // NP passes at once, block by block across the passes
+  template <int NP>
+  __device__ __forceinline__ void dist_all(const v4i (&x)[NP][CPL], const uint32_t (&side2)[NP],
+                                           uint32_t (&out)[NP]) const {
+    v4f acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, qa[pp]),
+                                                         __builtin_bit_cast(v8bf, x[p][pp]),
+                                                         acc[p], 0, 0, 0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) out[p] = finish(acc[p], side2[p]);
   }
   __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
     return keep_f32(d, best, num, den);
@@ -429,13 +520,18 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 #pragma unroll
         for (int pp = 0; pp < CPL; ++pp) {
           const int off = 16 * (sub + G * pp);
-          if (ok && off < a.row_bytes)
+          if (ok && off < a.coord_bytes)
             xv[buf][q][pp] = *reinterpret_cast<const v4i*>(row + off);
           else
             xv[buf][q][pp] = v4i{0, 0, 0, 0};
         }
         if (Score::kSide) sv[buf][q] = ok ? a.side[cidG[p]] : 0u;
-        if (Score::kSide2) sv2[buf][q] = ok ? a.side2[cidG[p]] : 0u;
+        if (Score::kSide2) {
+          if (a.side2_off >= 0)
+            sv2[buf][q] = ok ? *reinterpret_cast<const uint32_t*>(row + a.side2_off) : 0u;
+          else
+            sv2[buf][q] = ok ? a.side2[cidG[p]] : 0u;
+        }
         if (PART) pg[p] = ok ? a.node_part[cidG[p]] : -1;
         if (LISTS) {
 #pragma unroll
@@ -477,7 +573,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       // than G, only those passes are computed.
       uint32_t dg[G];
       uint32_t d = 0xffffffffu;
-      auto pass = [&](int p, int buf, int q) __attribute__((always_inline)) {
+      auto stage = [&](int p, int buf, int q) __attribute__((always_inline)) {
         const int c = p * SLOTS + slot;
         if (LISTS) {
 #pragma unroll
@@ -487,6 +583,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
               *reinterpret_cast<v4i*>(lists + c * LROW + 4 * chunk) = lv[buf][q][lc];
           }
         }
+      };
+      auto pass = [&](int p, int buf, int q) __attribute__((always_inline)) {
+        stage(p, buf, q);
         uint32_t dd;
         if constexpr (Score::kSide2)
           dd = sc.dist(xv[buf][q], sv[buf][q], sv2[buf][q]);
@@ -511,8 +610,19 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         else
           to_lane(0);
       } else if (NG == 1) {
+        if constexpr (Score::kBatch) {
+          // every pass's scores at once: the passes' dependent chains are
+          // independent of each other and interleave
 #pragma unroll
-        for (int p = 0; p < G; ++p) pass(p, 0, p);
+          for (int p = 0; p < G; ++p) stage(p, 0, p);
+          uint32_t dd[G];
+          sc.dist_all(xv[0], sv2[0], dd);
+#pragma unroll
+          for (int p = 0; p < G; ++p) dg[p] = cidG[p] >= 0 ? dd[p] : 0xffffffffu;
+        } else {
+#pragma unroll
+          for (int p = 0; p < G; ++p) pass(p, 0, p);
+        }
 #pragma unroll
         for (int p = 0; p < G; ++p) to_lane(p);
       } else {

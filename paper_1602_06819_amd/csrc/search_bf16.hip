@@ -17,6 +17,18 @@
 namespace knng {
 
 hipError_t launch_search_bf16(const SearchArgs& a, hipStream_t s, unsigned grid, size_t lds) {
+  // KNNG_SCORE_BF16_MFMA (rows of up to 128 coordinates carrying their
+  // norm) on the matrix cores (ScoreBF16M): 16 candidates per pass, 4 lanes
+  // per row, one 16-byte chunk per lane per 32-coordinate MFMA block.  With
+  // one wavefront per query the MFMA latency lies on every step's chain:
+  // measured slower than the VALU form, which is the default.
+  if (a.side2_off >= 0) {
+    if (a.dim <= 32) return launch_search_t<ScoreBF16M<1>, 4, 1, 1, 8>(a, s, grid, lds);
+    if (a.dim <= 64) return launch_search_t<ScoreBF16M<2>, 4, 2, 1, 8>(a, s, grid, lds);
+    if (a.dim <= 96) return launch_search_t<ScoreBF16M<3>, 4, 3, 2, 4>(a, s, grid, lds);
+    if (a.dim <= 128) return launch_search_t<ScoreBF16M<4>, 4, 4, 2, 4>(a, s, grid, lds);
+  }
+  // VALU dot products.
   // lists of up to 16 ids: 4 lanes per row (a list scan is one pass of 16);
   // longer lists: 2 lanes per row (32 candidates per pass)
   if (a.dim <= 64)

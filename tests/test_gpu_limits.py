@@ -116,6 +116,7 @@ def _d64(X, Q, ids):
     ("exact", 64, 50), ("exact", 128, 50), ("exact", 256, 20), ("exact", 256, 50),
     ("bf16", 128, 50), ("bf16", 256, 10), ("bf16", 512, 20),
     ("fp8", 256, 50), ("fp8", 512, 10), ("fp8", 1024, 20),
+    ("bf16m", 32, 20), ("bf16m", 64, 10), ("bf16m", 96, 10), ("bf16m", 128, 50),
 ])
 def test_float_search_at_row_size_limits(G, score, dim, k):
     import torch

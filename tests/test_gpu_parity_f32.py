@@ -101,7 +101,8 @@ def same_sequence(ref_d, got_d):
 
 
 @pytest.mark.parametrize("score,dim", [("bf16", 40), ("fp8", 40), ("exact", 40),
-                                       ("bf16", 300), ("fp8", 960)])
+                                       ("bf16", 300), ("fp8", 960), ("bf16m", 40),
+                                       ("bf16m", 128)])
 def test_ingest_rows_match_quantizers(G, score, dim):
     import torch
     X = f32_points(3, 300, dim) * 7.0
@@ -111,11 +112,22 @@ def test_ingest_rows_match_quantizers(G, score, dim):
     g = G.KnnGraph.build_exact(cfg_for(G, dim, 5, 300, 8, score=score), torch.from_numpy(X).cuda())
     rows, scale = g.rows()
     rows = rows.cpu().numpy()
-    if score == "bf16":
-        assert rows.shape[1] == -(-2 * dim // 16) * 16
-        got = rows.view(np.uint16)[:, :dim]
-        assert np.array_equal(got, O.quantize.bf16_bits(X))
-        assert not rows.view(np.uint16)[:, dim:].any()
+    if score in ("bf16", "bf16m"):
+        coord = -(-2 * dim // 16) * 16
+        # rows scored on the matrix cores carry the float32 squared norm of
+        # the stored row in a 16-byte chunk
+        packed = score == "bf16m"
+        assert rows.shape[1] == coord + (16 if packed else 0)
+        got = rows[:, :coord].view(np.uint16)[:, :dim]
+        bits = O.quantize.bf16_bits(X)
+        assert np.array_equal(got, bits)
+        assert not rows[:, :coord].view(np.uint16)[:, dim:].any()
+        if packed:
+            tail = rows[:, coord:].view(np.float32)
+            vals = O.quantize.bf16_value(bits).astype(np.float64)
+            want = (vals * vals).sum(axis=1)
+            assert np.allclose(tail[:, 0], want, rtol=dim * 2.0 ** -23, atol=0)
+            assert not tail[:, 1:].any()
     elif score == "fp8":
         codes, s = O.quantize.fp8_rows(X)
         assert rows.shape[1] == -(-dim // 16) * 16
@@ -129,7 +141,8 @@ def test_ingest_rows_match_quantizers(G, score, dim):
 
 @pytest.mark.parametrize("n,dim,k,score", [(2500, 128, 20, "bf16"), (1100, 96, 10, "bf16"),
                                            (700, 37, 7, "bf16"), (300, 200, 50, "bf16"),
-                                           (600, 960, 50, "fp8"), (900, 300, 20, "bf16")])
+                                           (600, 960, 50, "fp8"), (900, 300, 20, "bf16"),
+                                           (1100, 96, 10, "bf16m")])
 def test_exact_graph_float(G, n, dim, k, score):
     import torch
     X = f32_points(11 + dim, n, dim)
@@ -147,7 +160,7 @@ def test_exact_graph_float(G, n, dim, k, score):
     assert agree > 0.999
 
 
-@pytest.mark.parametrize("score", ["bf16", "fp8", "exact"])
+@pytest.mark.parametrize("score", ["bf16", "fp8", "exact", "bf16m"])
 def test_search_float_invariants_and_exhaustive(G, score):
     import torch
     n, dim, k = 3000, 128, 20
@@ -213,7 +226,8 @@ def test_search_float32_scores_follow_oracle(G):
     assert same >= 0.95 * len(Q)
 
 
-@pytest.mark.parametrize("score,batches", [("bf16", [256, 100, 1]), ("exact", [256, 77]),
+@pytest.mark.parametrize("score,batches", [("bf16", [256, 100, 1]), ("bf16m", [256, 100, 1]),
+                                            ("exact", [256, 77]),
                                            ("fp8", [128])])
 def test_insert_float(G, score, batches):
     import torch

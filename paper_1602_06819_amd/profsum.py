@@ -3,10 +3,15 @@
     python -m paper_1602_06819_amd.profsum trace  <dir> <out.md> "<command>"
     python -m paper_1602_06819_amd.profsum pmc    <fetch_dir> <write_dir> <out.json> \
         "<fetch command>" "<write command>" <copy_bytes>
+    python -m paper_1602_06819_amd.profsum pmc-serve <fetch_dir> <write_dir> <out.json> \
+        "<fetch command>" "<write command>" <copy_bytes> '<run shape json>'
 
 `trace` reads a `--kernel-trace --stats -f csv` run and writes per-kernel
 statistics, split by grid size (one kernel serves batches, single points
-and query sets).  `pmc` reads one `--pmc FETCH_SIZE` and one
+and query sets), and per kernel over all its grids.  `pmc-serve` writes the
+record of the serving run: the bfloat16 search's scaled HBM bytes averaged
+over all its dispatches (epochs differ in size), with the run shape they
+were taken on.  `pmc` reads one `--pmc FETCH_SIZE` and one
 `--pmc WRITE_SIZE` run, scales both by what the counters read for the
 calibration copy of `copy_bytes` bytes, and writes the bytes per dispatch
 of the search kernel together with the hash of its source, so that a stale
@@ -29,6 +34,7 @@ SEARCH_SOURCES = ["csrc/search.h", "csrc/device.h", "csrc/common.h", "csrc/inter
 SEARCH_UNITS = {"i8": ("search_u8.hip", "k_search<knng::ScoreI8"),
                 "bf16": ("search_bf16.hip", "k_search<knng::ScoreBF16")}
 SEARCH_KERNEL = SEARCH_UNITS["i8"][1]
+MAX_GRID_ROWS = 16        # rows of the per-grid table (the per-kernel table covers all)
 
 
 def search_kernel_hash(fmt: str = "i8") -> str:
@@ -79,9 +85,23 @@ def write_trace(directory: str, out: str, command: str) -> None:
              "Durations in microseconds, per kernel and grid (threads in x).", "",
              "| kernel | grid x | wg | calls | avg us | min us | max us | total us | % |",
              "|---|---|---|---|---|---|---|---|---|"]
-    for (name, grid, wg), v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+    rows = sorted(stats.items(), key=lambda kv: -sum(kv[1]))
+    for (name, grid, wg), v in rows[:MAX_GRID_ROWS]:
         lines.append(f"| `{_short(name)}` | {grid} | {wg} | {len(v)} | {sum(v) / len(v):.1f} | "
                      f"{min(v):.1f} | {max(v):.1f} | {sum(v):.1f} | {100 * sum(v) / total:.1f} |")
+    if len(rows) > MAX_GRID_ROWS:
+        rest = rows[MAX_GRID_ROWS:]
+        lines.append(f"| ({len(rest)} more kernel/grid rows, {sum(len(v) for _, v in rest)} "
+                     f"calls) | | | | | | | {sum(sum(v) for _, v in rest):.1f} | "
+                     f"{100 * sum(sum(v) for _, v in rest) / total:.1f} |")
+    by_kernel = defaultdict(list)
+    for (name, _grid, _wg), v in stats.items():
+        by_kernel[name].extend(v)
+    lines += ["", "Per kernel, all grids:", "",
+              "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
+    for name, v in sorted(by_kernel.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{_short(name)}` | {len(v)} | {sum(v) / len(v):.1f} | {sum(v):.1f} | "
+                     f"{100 * sum(v) / total:.1f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -137,6 +157,52 @@ def write_pmc(fetch_dir: str, write_dir: str, out: str, fetch_cmd: str, write_cm
         json.dump(rec, f, indent=1)
 
 
+def _copy_scale(table, counter: str, copy_bytes: int):
+    """Bytes per counter unit from the run's calibration copy (the largest
+    copy dispatch), or None."""
+    best = None
+    for (name, _grid, cname), v in table.items():
+        if "copy" in name and cname == counter and (best is None or max(v) > best):
+            best = max(v)
+    return copy_bytes / (best * 1024.0) if best else None
+
+
+def write_pmc_serve(fetch_dir: str, write_dir: str, out: str, fetch_cmd: str, write_cmd: str,
+                    copy_bytes: int, run_shape: dict) -> None:
+    fetch = counter_table(fetch_dir)
+    write = counter_table(write_dir)
+    kernel = SEARCH_UNITS["bf16"][1]
+    scale_f = _copy_scale(fetch, "FETCH_SIZE", copy_bytes)
+    scale_w = _copy_scale(write, "WRITE_SIZE", copy_bytes)
+
+    def per_dispatch(table, counter):
+        vals = [x for (name, _g, cname), v in table.items()
+                if kernel in name and cname == counter for x in v]
+        return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+    f_kib, nf = per_dispatch(fetch, "FETCH_SIZE")
+    w_kib, nw = per_dispatch(write, "WRITE_SIZE")
+    total = None
+    if f_kib is not None and w_kib is not None and scale_f and scale_w:
+        total = 1024.0 * (f_kib * scale_f + w_kib * scale_w)
+    rec = {
+        "kernel": "k_search (bf16 rows), serving run",
+        "source_hash": search_kernel_hash("bf16"),
+        "run": run_shape,
+        "fetch_command": fetch_cmd,
+        "write_command": write_cmd,
+        "copy_bytes": copy_bytes,
+        "fetch_scale": scale_f,
+        "write_scale": scale_w,
+        "dispatches": [nf, nw],
+        "fetch_kib_per_dispatch": f_kib,
+        "write_kib_per_dispatch": w_kib,
+        "bytes_per_dispatch": total,
+    }
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "trace":
@@ -144,5 +210,8 @@ if __name__ == "__main__":
     elif mode == "pmc":
         write_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
                   int(sys.argv[7]))
+    elif mode == "pmc-serve":
+        write_pmc_serve(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
+                        int(sys.argv[7]), json.loads(sys.argv[8]))
     else:
         raise SystemExit(__doc__)

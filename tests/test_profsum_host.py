@@ -105,3 +105,44 @@ def test_search_algorithmic_bytes():
     assert b == pytest.approx(100 * 256 + 10 * 80 + 512 + 160 + 40 * 512)
     b = bench.search_algorithmic_bytes("fp8", 960, 50, 1, 1.0, 0.0)
     assert b == pytest.approx(964 + 3840 + 400 + 64 * 3840)
+
+
+def test_serving_counter_record_and_traffic(tmp_path, monkeypatch):
+    """The serving record averages the bfloat16 search over all its
+    dispatches (epochs differ in size) and is reported only for its kernel
+    source and run shape."""
+    search = "void knng::k_search<knng::ScoreBF16<4, 4>, 4, 4, 16, true>(knng::SearchArgs)"
+    other = "void knng::k_search<knng::ScoreI8<2, 2>, 2, 2, 16, false>(knng::SearchArgs)"
+    copy_bytes = 256 << 20
+    counters(str(tmp_path / "f" / "pmc_counter_collection.csv"), [
+        {"Kernel_Name": COPY, "Grid_Size": 65536, "Counter_Name": "FETCH_SIZE", "Counter_Value": 131072},
+        {"Kernel_Name": search, "Grid_Size": 1048576, "Counter_Name": "FETCH_SIZE", "Counter_Value": 3000},
+        {"Kernel_Name": search, "Grid_Size": 262144, "Counter_Name": "FETCH_SIZE", "Counter_Value": 1000},
+        {"Kernel_Name": other, "Grid_Size": 16384, "Counter_Name": "FETCH_SIZE", "Counter_Value": 99999},
+    ])
+    counters(str(tmp_path / "w" / "pmc_counter_collection.csv"), [
+        {"Kernel_Name": COPY, "Grid_Size": 65536, "Counter_Name": "WRITE_SIZE", "Counter_Value": 262144},
+        {"Kernel_Name": search, "Grid_Size": 1048576, "Counter_Name": "WRITE_SIZE", "Counter_Value": 30},
+        {"Kernel_Name": search, "Grid_Size": 262144, "Counter_Name": "WRITE_SIZE", "Counter_Value": 10},
+    ])
+    from datagen import get_workload
+    w = get_workload("serve-f32-d96-1m-2m")
+    shape = bench.serving_run_shape(w, 20, 50_000, 16384, 4096)
+    out = str(tmp_path / "rec.json")
+    profsum.write_pmc_serve(str(tmp_path / "f"), str(tmp_path / "w"), out, "fc", "wc", copy_bytes,
+                            shape)
+    rec = json.load(open(out))
+    assert rec["dispatches"] == [2, 2]
+    assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
+    # mean fetch 2000 KiB x 2 + mean write 20 KiB x 1, per dispatch
+    assert rec["bytes_per_dispatch"] == pytest.approx(1024.0 * (2000 * 2.0 + 20 * 1.0))
+    profiles = tmp_path / "profiles"
+    profiles.mkdir()
+    (profiles / f"traffic_k_search_{w.name}.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_serving_traffic(w.name, shape) == pytest.approx(rec["bytes_per_dispatch"])
+    other_shape = dict(shape, speedup=10)
+    assert bench.recorded_serving_traffic(w.name, other_shape) is None
+    rec["source_hash"] = "0" * 16
+    (profiles / f"traffic_k_search_{w.name}.json").write_text(json.dumps(rec))
+    assert bench.recorded_serving_traffic(w.name, shape) is None

@@ -23,9 +23,11 @@ recall@k of the final graph against its exact graph (all edges, new nodes,
 old nodes), query throughput inside the mix, similarity evaluations per
 insert, the search kernel's fraction of the HBM roofline (algorithmic bytes
 over its measured time), the plain per-point (batch = 1) insertion rate on
-the same GPU, a search-only comparison of bfloat16 and float32 ("FP32
-plain") scoring, and the CPU oracle timed on a bounded sample with one
-process and with one process per host core.
+the same GPU, the naive exact insertion of Section 2.1 (every new point
+compared with every node, brute-force tiles) on the same inserts, a
+search-only comparison of bfloat16 and float32 ("FP32 plain") scoring, and
+the CPU oracle timed on a bounded sample with one process and with one
+process per host core.
 
 The other workloads (``--workload u8-d64-n100k-b256``, ``f32-d128-n1m-b1024``,
 ``f32-d960-n500k-b512-fp8``) time fixed-size insert batches (one batch per
@@ -82,6 +84,8 @@ def parse():
                     help="serving: oracle worker processes (at most the host's cores)")
     ap.add_argument("--per-point", type=int, default=256,
                     help="points inserted one at a time for the batch=1 baseline")
+    ap.add_argument("--no-naive", action="store_true",
+                    help="skip the naive exact insertion baseline (Section 2.1)")
     ap.add_argument("--plain-compare", type=int, default=4096,
                     help="serving: points searched with bfloat16 and float32 scoring")
     ap.add_argument("--no-recall", action="store_true")
@@ -319,6 +323,20 @@ def bench_batches(args, w) -> dict:
         del gp
         log(f"[bench] per-point insertion (b=1): {per_point:.0f} inserts/s")
 
+    # ---- the naive method (Section 2.1) on the same GPU: the same batches -----------
+    naive = None
+    if not args.no_naive:
+        gn = KnnGraph.build_exact(cfg, Xd[:n0])
+        torch.cuda.synchronize()
+        tn0 = time.perf_counter()
+        for s in range(K):
+            gn.insert_exact(Xd[n0 + s * b:n0 + (s + 1) * b])
+        torch.cuda.synchronize()
+        naive = inserts / (time.perf_counter() - tn0)
+        gn.close()
+        del gn
+        log(f"[bench] naive exact insertion (brute force, batches of {b}): {naive:.0f} inserts/s")
+
     # ---- calibration copy for the HBM byte counters ----------------------------------
     if args.calibrate_copy > 0:
         calibration_copy(args.calibrate_copy, dev)
@@ -363,6 +381,7 @@ def bench_batches(args, w) -> dict:
         "build_exact_ms": build_ms,
         "stage_ms": {k: round(v[0], 3) for k, v in stage.items() if v[1]},
         "per_point_inserts_per_s": per_point,
+        "naive_exact_inserts_per_s": naive,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -701,6 +720,29 @@ def bench_serving(args, w) -> dict:
         del gp
         log(f"[bench] per-point insertion (b=1): {per_point:.0f} inserts/s")
 
+    # ---- the naive method (Section 2.1) on the same GPU: the same inserts -----------
+    naive = None
+    if not args.no_naive:
+        gn = KnnGraph.load(cfg, Xd[:n0], ids0, d0)
+        sizes = [sum(r.size for r in reqs if r.kind == "insert") for reqs in steps[:K]]
+        torch.cuda.synchronize()
+        tn0 = time.perf_counter()
+        lo = 0
+        for total in sizes:
+            end = lo + total
+            while lo < end:
+                hi = min(end, lo + ep_ins)
+                gn.insert_exact(Xins[lo:hi])
+                lo = hi
+        torch.cuda.synchronize()
+        naive = inserts / (time.perf_counter() - tn0)
+        assert gn.n == n_final
+        gn.close()
+        del gn
+        torch.cuda.empty_cache()
+        log(f"[bench] naive exact insertion (brute force, batches of {ep_ins}): "
+            f"{naive:.0f} inserts/s")
+
     # ---- calibration copy for the HBM byte counters ----------------------------------
     if args.calibrate_copy > 0:
         calibration_copy(args.calibrate_copy, dev)
@@ -748,6 +790,7 @@ def bench_serving(args, w) -> dict:
         "stage_ms": {k: round(v[0], 3) for k, v in stage.items() if v[1]},
         "search_alone": plain,
         "per_point_inserts_per_s": per_point,
+        "naive_exact_inserts_per_s": naive,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

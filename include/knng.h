@@ -230,6 +230,21 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
                               int32_t* stats_dev, hipStream_t stream);
 
 /*
+ * The naive method of Section 2.1 in online form, the baseline the paper's
+ * search is measured against: insert b points (ids n .. n+b-1) by
+ * comparing each with every node.  Each new node's list is its k best among
+ * all n + b nodes, and each pre-batch node's list becomes the k best of
+ * itself and the b new nodes, by (distance, id).  From an exact graph (e.g.
+ * knng_build_exact) the graph stays exact; costs b (n + b) + n b distance
+ * evaluations (brute-force tiles on the matrix cores, as knng_build_exact).
+ *  x_dev          [b][dim] points, device.
+ *  first_id_host  out: n, or NULL.
+ * Needs n + b <= capacity (KNNG_ECAPACITY otherwise) and b <= max_batch.
+ */
+knng_status knng_insert_exact(knng_graph* g, const void* x_dev, int64_t b,
+                              int64_t* first_id_host, hipStream_t stream);
+
+/*
  * Read-only k-nn query of m points on the current graph (the k-nn search
  * problem of Section 2.2, answered with the iGNNS search of Section 3):
  * iGNNS with the keys 2^62 + s, where s counts every query this handle has

@@ -28,7 +28,7 @@ EXPORTED = [
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
     "knng_epoch", "knng_search_gnns", "knng_partition_scratch_bytes", "knng_partition",
     "knng_search_partitioned_scratch_bytes", "knng_search_partitioned",
-    "knng_search_partitioned_noalloc",
+    "knng_search_partitioned_noalloc", "knng_insert_exact",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -80,6 +80,8 @@ def _load() -> ctypes.CDLL:
     lib.knng_search.restype = ctypes.c_int
     lib.knng_insert_batch.argtypes = [vp, vp, i64, P(i64), vp, vp, vp]
     lib.knng_insert_batch.restype = ctypes.c_int
+    lib.knng_insert_exact.argtypes = [vp, vp, i64, P(i64), vp]
+    lib.knng_insert_exact.restype = ctypes.c_int
     lib.knng_query.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     lib.knng_query.restype = ctypes.c_int
     lib.knng_get_lists.argtypes = [vp, i64, i64, vp, vp, vp]

@@ -493,39 +493,45 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipSt
   return KNNG_OK;
 }
 
-// Exact lists of the n stored points (uint8: int8 MFMA tiles, split over
-// the database for small n; float32: float32 MFMA candidates per chunk of
-// nodes, then the float32 re-rank).
-knng_status exact_lists(knng_graph* g, int64_t n, hipStream_t stream) {
+// Exact lists of the stored nodes q_first .. q_first + nq - 1 against the
+// stored nodes d_first .. d_first + nd - 1 (uint8: int8 MFMA tiles, split
+// over the database when the queries are few; float32: float32 MFMA
+// candidates per chunk of queries, then the float32 re-rank), excluding a
+// node from its own list if `exclude_self`; k entries per row at out_ids /
+// out_d with row stride out_stride.
+knng_status exact_lists_range(knng_graph* g, int64_t q_first, int64_t nq, int64_t d_first,
+                              int64_t nd, bool exclude_self, int32_t* out_ids, int32_t* out_d,
+                              int out_stride, hipStream_t stream, bool split_ok = true) {
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
-  int32_t* ids = at<int32_t>(g->st, S.off_ids);
-  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  if (nq <= 0 || nd <= 0) return KNNG_OK;
   Timed t(g, KNNG_STAGE_EXACT, stream);
+  const int rb = S.is_float ? S.mstride * 4 : S.row_bytes;
+  const char* rows = S.is_float ? at<char>(g->st, S.off_master) : at<char>(g->st, S.off_vec);
+  const uint32_t* norms = at<uint32_t>(g->st, S.off_norms);
   ExactArgs a{};
-  a.qvec = S.is_float ? (const void*)at<float>(g->st, S.off_master)
-                      : (const void*)at<int8_t>(g->st, S.off_vec);
-  a.qnorm = at<uint32_t>(g->st, S.off_norms);
-  a.nq = (int32_t)n;
-  a.q_id_base = 0;
-  a.dvec = a.qvec;
-  a.dnorm = a.qnorm;
-  a.nd = (int32_t)n;
-  a.d_id_base = 0;
-  a.row_bytes = S.is_float ? S.mstride * 4 : S.row_bytes;
+  a.qvec = rows + q_first * rb;
+  a.qnorm = norms + q_first;
+  a.nq = (int32_t)nq;
+  a.q_id_base = (int32_t)q_first;
+  a.dvec = rows + d_first * rb;
+  a.dnorm = norms + d_first;
+  a.nd = (int32_t)nd;
+  a.d_id_base = (int32_t)d_first;
+  a.row_bytes = rb;
   a.k = S.k;
-  a.exclude_self = 1;
+  a.exclude_self = exclude_self ? 1 : 0;
   if (S.is_float) {
     const int km = exact_km(S.k);
     uint64_t* cand = at<uint64_t>(g->ws, W.off_cand);
-    for (int64_t q0 = 0; q0 < n; q0 += W.cand_rows) {
-      const int64_t nq = n - q0 < W.cand_rows ? n - q0 : W.cand_rows;
+    for (int64_t q0 = 0; q0 < nq; q0 += W.cand_rows) {
+      const int64_t cnt = nq - q0 < W.cand_rows ? nq - q0 : W.cand_rows;
       ExactArgs c = a;
-      c.qvec = at<float>(g->st, S.off_master) + q0 * S.mstride;
-      c.qnorm = at<uint32_t>(g->st, S.off_norms) + q0;
-      c.nq = (int32_t)nq;
-      c.q_id_base = (int32_t)q0;
-      c.split_len = (int32_t)n;
+      c.qvec = rows + (q_first + q0) * rb;
+      c.qnorm = norms + q_first + q0;
+      c.nq = (int32_t)cnt;
+      c.q_id_base = (int32_t)(q_first + q0);
+      c.split_len = (int32_t)nd;
       c.nsplit = 1;
       c.cand = cand;
       KNNG_TRY(launch_exact_f32(c, km, stream), "exact launch");
@@ -533,37 +539,76 @@ knng_status exact_lists(knng_graph* g, int64_t n, hipStream_t stream) {
       r.rows = at<float>(g->st, S.off_master);
       r.stride = S.mstride;
       r.dim = S.dim;
-      r.q_id_base = (int32_t)q0;
-      r.nq = (int32_t)nq;
+      r.q_id_base = (int32_t)(q_first + q0);
+      r.nq = (int32_t)cnt;
       r.cand = cand;
       r.km = km;
       r.k = S.k;
-      r.out_ids = ids + q0 * S.k_pad;
-      r.out_d = dist + q0 * S.k_pad;
-      r.out_stride = S.k_pad;
+      r.out_ids = out_ids + q0 * out_stride;
+      r.out_d = out_d + q0 * out_stride;
+      r.out_stride = out_stride;
       KNNG_TRY(launch_rerank_f32(r, stream), "re-rank launch");
     }
     return KNNG_OK;
   }
-  a.out_ids = ids;
-  a.out_d = dist;
-  a.out_stride = S.k_pad;
+  a.out_ids = out_ids;
+  a.out_d = out_d;
+  a.out_stride = out_stride;
   a.partial = at<uint64_t>(g->ws, W.off_partial);
   const int qt = S.k_pad == 64 ? 1 : 2;
-  const int64_t bx = (n + 64 * qt - 1) / (64 * qt);
-  int64_t nsplit = (1024 + bx - 1) / bx;
+  const int64_t bx = (nq + 64 * qt - 1) / (64 * qt);
+  // (splits write partial lists into the workspace; a caller whose output
+  // lives there passes split_ok = false)
+  int64_t nsplit = split_ok ? (1024 + bx - 1) / bx : 1;
   if (nsplit > 64) nsplit = 64;
-  while (nsplit > 1 && nsplit * n > W.partial_lists) --nsplit;
+  while (nsplit > 1 && nsplit * nq > W.partial_lists) --nsplit;
   if (nsplit < 1) nsplit = 1;
-  int64_t split_len = round_up((n + nsplit - 1) / nsplit, 64);
-  nsplit = (n + split_len - 1) / split_len;
+  int64_t split_len = round_up((nd + nsplit - 1) / nsplit, 64);
+  nsplit = (nd + split_len - 1) / split_len;
   a.split_len = (int32_t)split_len;
   a.nsplit = (int32_t)nsplit;
   KNNG_TRY(launch_exact_u8(a, stream), "exact launch");
   if (nsplit > 1)
-    KNNG_TRY(launch_split_merge(a.partial, (int32_t)n, (int32_t)nsplit, S.k, ids, dist, S.k_pad,
-                                stream),
+    KNNG_TRY(launch_split_merge(a.partial, (int32_t)nq, (int32_t)nsplit, S.k, out_ids, out_d,
+                                out_stride, stream),
              "split merge launch");
+  return KNNG_OK;
+}
+
+// Exact lists of the n stored points.
+knng_status exact_lists(knng_graph* g, int64_t n, hipStream_t stream) {
+  return exact_lists_range(g, 0, n, 0, n, true, at<int32_t>(g->st, g->S.off_ids),
+                           at<int32_t>(g->st, g->S.off_dist), g->S.k_pad, stream);
+}
+
+// The naive method of Section 2.1 applied to a batch of b points stored at
+// ids n .. n+b-1: each new node's list by brute force over all n + b nodes,
+// and each pre-batch node's list merged with its k best among the b new
+// nodes (tiles of old nodes against the batch, through a buffer of
+// PARTIAL_LISTS rows).  From an exact graph this keeps the graph exact.
+knng_status insert_exact_after_ingest(knng_graph* g, int64_t b, hipStream_t stream) {
+  const StorageLayout& S = g->S;
+  const WorkspaceLayout& W = g->W;
+  const int64_t n = g->n;
+  int32_t* ids = at<int32_t>(g->st, S.off_ids);
+  int32_t* dist = at<int32_t>(g->st, S.off_dist);
+  knng_status s = exact_lists_range(g, n, b, 0, n + b, true, ids + n * S.k_pad,
+                                    dist + n * S.k_pad, S.k_pad, stream);
+  if (s != KNNG_OK) return s;
+  int32_t* tmp_ids = at<int32_t>(g->ws, W.off_partial);
+  const int64_t chunk = W.partial_lists;
+  int32_t* tmp_d = tmp_ids + chunk * S.k_pad;
+  for (int64_t q0 = 0; q0 < n; q0 += chunk) {
+    const int64_t cnt = n - q0 < chunk ? n - q0 : chunk;
+    if ((s = exact_lists_range(g, q0, cnt, n, b, false, tmp_ids, tmp_d, S.k_pad, stream,
+                               false)) != KNNG_OK)
+      return s;
+    Timed t(g, KNNG_STAGE_MERGE, stream);
+    KNNG_TRY(launch_merge_lists(ids + q0 * S.k_pad, dist + q0 * S.k_pad, tmp_ids, tmp_d,
+                                S.k_pad, S.k, cnt, S.pad, stream),
+             "merge launch");
+  }
+  g->n = n + b;
   return KNNG_OK;
 }
 
@@ -1008,6 +1053,29 @@ knng_status knng_insert_batch(knng_graph* g, const void* x_dev, int64_t b,
     return st;
   const int64_t n = g->n;
   if ((st = insert_after_search(g, b, sims_dev, stats_dev, stream)) != KNNG_OK) return st;
+  if (first_id_host) *first_id_host = n;
+  return ok();
+}
+
+knng_status knng_insert_exact(knng_graph* g, const void* x_dev, int64_t b,
+                              int64_t* first_id_host, hipStream_t stream) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+  knng_status s;
+  if (b == 0) {
+    if (first_id_host) *first_id_host = g->n;
+    return ok();
+  }
+  if (b < 0) return fail(KNNG_EINVAL, "b must be >= 0");
+  if ((s = check_ptr(x_dev, "x_dev")) != KNNG_OK) return s;
+  if (b > g->W.M)
+    return fail(KNNG_ECAPACITY, "batch %lld exceeds max_batch %lld", (long long)b,
+                (long long)g->W.M);
+  if (g->n + b > g->S.cap)
+    return fail(KNNG_ECAPACITY, "n %lld + batch %lld exceeds capacity %lld", (long long)g->n,
+                (long long)b, (long long)g->S.cap);
+  const int64_t n = g->n;
+  if ((s = ingest(g, x_dev, b, n, stream)) != KNNG_OK) return s;
+  if ((s = insert_exact_after_ingest(g, b, stream)) != KNNG_OK) return s;
   if (first_id_host) *first_id_host = n;
   return ok();
 }

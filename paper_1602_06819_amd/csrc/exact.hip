@@ -390,4 +390,52 @@ hipError_t launch_rerank_f32(const RerankArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Each row of (ids, d) becomes the first k of itself and the sorted row of
+// (tids, td), by (distance, id): one wavefront per row, every entry placed
+// at its rank in the union (its index plus the entries of the other row
+// before it; ids are distinct, so keys never tie).
+__global__ __launch_bounds__(64) void k_merge_lists(int32_t* ids, int32_t* d, const int32_t* tids,
+                                                    const int32_t* td, int k_pad, int k,
+                                                    int64_t count, int32_t pad) {
+  const int lane = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < count; r += gridDim.x) {
+    const int64_t base = r * k_pad;
+    const int32_t ia = lane < k ? ids[base + lane] : -1;
+    const int32_t ib = lane < k ? tids[base + lane] : -1;
+    const uint64_t ka = ia >= 0 ? make_key((uint32_t)d[base + lane], ia) : KEY_INF;
+    const uint64_t kb = ib >= 0 ? make_key((uint32_t)td[base + lane], ib) : KEY_INF;
+    int ra = lane, rb = lane;
+    for (int t = 0; t < k; ++t) {
+      const uint64_t oa = shfl_u64(ka, t);
+      const uint64_t ob = shfl_u64(kb, t);
+      rb += oa < kb ? 1 : 0;
+      ra += ob < ka ? 1 : 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (ka != KEY_INF && ra < k) {
+      ids[base + ra] = key_id(ka);
+      d[base + ra] = (int32_t)key_dist(ka);
+    }
+    if (kb != KEY_INF && rb < k) {
+      ids[base + rb] = key_id(kb);
+      d[base + rb] = (int32_t)key_dist(kb);
+    }
+    // entries past the union's length become padding
+    const int total = __popcll(__ballot(ka != KEY_INF)) + __popcll(__ballot(kb != KEY_INF));
+    if (lane < k && lane >= total) {
+      ids[base + lane] = -1;
+      d[base + lane] = pad;
+    }
+  }
+}
+
+hipError_t launch_merge_lists(int32_t* ids, int32_t* d, const int32_t* tids, const int32_t* td,
+                              int k_pad, int k, int64_t count, int32_t pad, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t grid = count < 65536 ? count : 65536;
+  hipLaunchKernelGGL(k_merge_lists, dim3((unsigned)grid), dim3(64), 0, s, ids, d, tids, td, k_pad,
+                     k, count, pad);
+  return hipGetLastError();
+}
+
 }  // namespace knng

@@ -225,6 +225,8 @@ constexpr int BF16_MFMA_DIM = 128;
 hipError_t launch_ingest_u8(const IngestArgs& a, hipStream_t s);
 hipError_t launch_ingest_f32(const IngestF32Args& a, hipStream_t s);
 hipError_t launch_exact_u8(const ExactArgs& a, hipStream_t s);
+hipError_t launch_merge_lists(int32_t* ids, int32_t* d, const int32_t* tids, const int32_t* td,
+                              int k_pad, int k, int64_t count, int32_t pad, hipStream_t s);
 hipError_t launch_exact_f32(const ExactArgs& a, int km, hipStream_t s);
 hipError_t launch_rerank_f32(const RerankArgs& a, hipStream_t s);
 hipError_t launch_split_merge(const uint64_t* partial, int32_t nq, int32_t nsplit, int k,

@@ -169,6 +169,15 @@ class KnnGraph:
             return first.value, out, st
         return first.value, out
 
+    def insert_exact(self, x: torch.Tensor, stream=None) -> int:
+        """The naive method: insert a batch by comparing each point with every
+        node (the graph stays exact if it was); returns the first new id."""
+        x = self._as_points(x)
+        first = ctypes.c_int64(0)
+        check(_lib.lib.knng_insert_exact(self._h, _ptr(x), x.shape[0], ctypes.byref(first),
+                                         _stream(stream)))
+        return first.value
+
     def epoch(self, x: torch.Tensor | None, q: torch.Tensor | None, sims: bool = False,
               stats: bool = False, stream=None):
         """One serving epoch on the current snapshot: queries q and the insert

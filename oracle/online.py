@@ -105,17 +105,24 @@ def point_search_and_proposals(g, Y: np.ndarray, i: int, p: Params, record: bool
     return r, props, upd
 
 
-def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False):
+def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False, run_points=None):
     """Steps (i)-(iii) of a batch on the snapshot g: returns (search results,
     final lists F_i, proposals in emission order, update evaluations, sims).
     Reads from g only its points, node count and stored lists, so g may be
-    any snapshot that provides them (e.g. :class:`exact.LazyExactGraph`)."""
+    any snapshot that provides them (e.g. :class:`exact.LazyExactGraph`).
+    The batch points are independent in steps (i) and (iii): ``run_points``
+    (optional) maps a list of point indices to their
+    :func:`point_search_and_proposals` results, in order -- e.g. over worker
+    processes; by default they run one after another."""
     n = g.n
     b = Y.shape[0]
     k = p.k
     # (i) search on the snapshot, and (iii) update proposals against the
     # snapshot lists, per batch point
-    per_point = [point_search_and_proposals(g, Y, i, p, record) for i in range(b)]
+    if run_points is None:
+        per_point = [point_search_and_proposals(g, Y, i, p, record) for i in range(b)]
+    else:
+        per_point = list(run_points(list(range(b))))
     search = [r for r, _, _ in per_point]
     # (ii) batch peers
     final_lists = []
@@ -144,12 +151,15 @@ def merge_proposals(g, proposals: list, k: int) -> dict:
     return {u: sorted(g.neighbour_pairs(u) + props)[:k] for u, props in by_target.items()}
 
 
-def insert_batch(g: OracleGraph, Y: np.ndarray, p: Params, record: bool = False) -> BatchResult:
-    """Insert the points Y (one batch) into g; g itself is not modified."""
+def insert_batch(g: OracleGraph, Y: np.ndarray, p: Params, record: bool = False,
+                 run_points=None) -> BatchResult:
+    """Insert the points Y (one batch) into g; g itself is not modified.
+    ``run_points`` as in :func:`search_and_propose`."""
     n = g.n
     b = Y.shape[0]
     k = p.k
-    search, final_lists, proposals, update_evals, sims = search_and_propose(g, Y, p, record)
+    search, final_lists, proposals, update_evals, sims = search_and_propose(g, Y, p, record,
+                                                                            run_points)
     # (iv) merge
     merged = merge_proposals(g, proposals, k)
     ids_new, dist_new = empty_lists(n + b, k, g.X.dtype)

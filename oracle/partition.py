@@ -14,11 +14,17 @@ Readings, where the paper leaves points open:
   In exact arithmetic: m beats m' iff
       (N - |C(m)| P) (1 + d(u, m')) > (N - |C(m')| P) (1 + d(u, m)),
   N = n num, P = p den; ties go to the smaller medoid index.
-* Update: the new medoid of a cluster is its member with the smallest sum
-  of dissimilarities to the cluster's members (ties: smaller id); the
-  paper's graph shortest paths are replaced by the dissimilarity itself,
-  the heuristic it already uses for the assign step.  An empty cluster
-  keeps its medoid.
+* Update (Section 6: the distance between two nodes is the length of the
+  shortest path in the graph between them, by Dijkstra): the graph is the
+  k-nn graph taken as undirected -- u and v are joined if either list holds
+  the other, with the stored distance of the pair as the edge's length --
+  restricted to the cluster's members (a search within a part moves only
+  through the part).  The new medoid of a cluster is the member u that
+  minimizes (members it cannot reach, sum of the path lengths from u to
+  the members it reaches, u): within a connected cluster, the member with
+  the smallest sum of path lengths, ties to the smaller id.  Sums are taken
+  over the members in increasing id order (exact integers for uint8
+  points).  An empty cluster keeps its medoid.
 * Iterations: a fixed number; each is an assign then an update; the
   partition is the last assignment.
 * Search of a partition: iGNNS restricted to the partition's nodes (the
@@ -28,11 +34,12 @@ Readings, where the paper leaves points open:
 
 from __future__ import annotations
 
+import heapq
 from fractions import Fraction
 
 import numpy as np
 
-from .distance import sqdist, sqdist_many
+from .distance import sqdist
 from .graph import OracleGraph, Params
 from .ignns import SearchResult, ignns
 from .restart import RestartOrder
@@ -75,30 +82,74 @@ def assign(X: np.ndarray, medoids: list[int], imb_num: int, imb_den: int) -> np.
     return part
 
 
-def update(X: np.ndarray, part: np.ndarray, medoids: list[int]) -> list[int]:
+def undirected_edges(ids: np.ndarray, dist: np.ndarray) -> dict:
+    """The k-nn graph as an undirected graph: {u: {v: length}}, u and v
+    joined if either list holds the other, the length being the stored
+    distance of the pair."""
+    adj: dict[int, dict] = {}
+    n, k = ids.shape
+    for u in range(n):
+        for j in range(k):
+            v = int(ids[u, j])
+            if v < 0:
+                continue
+            w = dist[u, j].item()
+            adj.setdefault(u, {})[v] = w
+            adj.setdefault(v, {})[u] = w
+    return adj
+
+
+def shortest_paths(adj: dict, source: int, allowed: set) -> dict:
+    """Dijkstra from `source` through the nodes of `allowed`: {node: length
+    of its shortest path} for every node it reaches."""
+    done: dict[int, object] = {}
+    heap = [(0, source)]
+    while heap:
+        d, u = heapq.heappop(heap)
+        if u in done:
+            continue
+        done[u] = d
+        for v, w in adj.get(u, {}).items():
+            if v in allowed and v not in done:
+                heapq.heappush(heap, (d + w, v))
+    return done
+
+
+def member_path_key(adj: dict, u: int, members: list) -> tuple:
+    """(members u cannot reach, sum of its path lengths to the others in
+    increasing id order, u) within the cluster `members` (sorted ids)."""
+    D = shortest_paths(adj, u, set(members))
+    tot = 0
+    for v in members:
+        if v in D:
+            tot = tot + D[v]
+    return (len(members) - len(D), tot, u)
+
+
+def update(ids: np.ndarray, dist: np.ndarray, part: np.ndarray, medoids: list[int],
+           adj: dict | None = None) -> list[int]:
+    """New medoids by graph shortest paths within each cluster (Section 6)."""
+    adj = undirected_edges(ids, dist) if adj is None else adj
     out = list(medoids)
     for m in range(len(medoids)):
-        members = np.nonzero(part == m)[0]
-        if len(members) == 0:
+        members = [int(u) for u in np.nonzero(part == m)[0]]
+        if not members:
             continue
-        best = None
-        for u in members:
-            s = sqdist_many(X[u], X[members])
-            tot = int(np.sum(s)) if X.dtype == np.uint8 else float(np.sum(s))
-            if best is None or (tot, int(u)) < best:
-                best = (tot, int(u))
-        out[m] = best[1]
+        out[m] = min(member_path_key(adj, u, members) for u in members)[2]
     return out
 
 
-def balanced_kmedoids(X: np.ndarray, p: int, iters: int, seed: int, imb_num: int = 1,
-                      imb_den: int = 1, medoids: list[int] | None = None):
-    """Returns (part [n], medoids [p])."""
+def balanced_kmedoids(X: np.ndarray, ids: np.ndarray, dist: np.ndarray, p: int, iters: int,
+                      seed: int, imb_num: int = 1, imb_den: int = 1,
+                      medoids: list[int] | None = None):
+    """Algorithm 4 on the points X and their k-nn graph (ids, dist): returns
+    (part [n], medoids [p])."""
     meds = initial_medoids(X.shape[0], p, seed) if medoids is None else list(medoids)
+    adj = undirected_edges(ids, dist)
     part = None
     for _ in range(iters):
         part = assign(X, meds, imb_num, imb_den)
-        meds = update(X, part, meds)
+        meds = update(ids, dist, part, meds, adj)
     return part, meds
 
 

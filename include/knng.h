@@ -285,12 +285,18 @@ knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* 
  * the restart permutation keyed 2^61 (seed `seed`).  Each of `iters`
  * iterations assigns the nodes in id order, each to the medoid maximizing
  * similarity * (1 - size / capacity) with similarity 1 / (1 + d) (exact
- * comparisons; ties to the smaller medoid index), then makes each part's
- * member with the smallest sum of dissimilarities to its part the new
- * medoid (ties: smaller id).
+ * comparisons; ties to the smaller medoid index), then computes each part's
+ * new medoid from shortest paths in the graph (Section 6): over the k-nn
+ * graph taken as undirected (u and v joined if either list holds the
+ * other; edge length = the stored distance of the pair), through the
+ * part's nodes only, the member that reaches the most members, then has
+ * the smallest sum of path lengths to them (summed in increasing id order;
+ * exact integers for uint8 graphs), then the smaller id.
  *  p              1 .. 64, at most n.   imb_num / imb_den in [1, 64].
  *  scratch_dev    device scratch of knng_partition_scratch_bytes(g, p)
- *                 bytes, 256-byte aligned (owned by the caller).
+ *                 bytes (about 20 n min(n, 256) bytes for the shortest-path
+ *                 slots, plus O(n (p + k))), 256-byte aligned (owned by the
+ *                 caller).
  *  part_dev       [n] int32 out: the part of every node (last assignment).
  *  medoids_dev    [p] int32 out: the medoids after the last update.
  */

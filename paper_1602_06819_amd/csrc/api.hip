@@ -745,17 +745,36 @@ void initial_medoids(int64_t n, int p, uint64_t seed, int32_t* out) {
   }
 }
 
+// Shortest-path scratch slots of the medoid update (one wavefront each).
+constexpr int64_t PATH_SLOTS = 256;
+
 struct PartScratch {
-  size_t off_D = 0, off_members = 0, off_offsets = 0, off_sums = 0, total = 0;
+  size_t off_D = 0, off_members = 0, off_offsets = 0, off_sums = 0, off_unreached = 0,
+         off_pos = 0, off_in_off = 0, off_in_src = 0, off_in_w = 0, off_counts = 0,
+         off_sp_dist = 0, off_sp_cur = 0, off_sp_next = 0, off_sp_inq = 0, total = 0;
+  int64_t slots = 0, slot_len = 0;
 };
 
-PartScratch part_scratch(int64_t n, int p) {
+PartScratch part_scratch(int64_t n, int p, int k) {
   PartScratch P;
   size_t cur = 0;
   P.off_D = take(cur, (size_t)n * p * 4);
   P.off_members = take(cur, (size_t)n * 4);
   P.off_offsets = take(cur, 65 * 4);
   P.off_sums = take(cur, (size_t)n * 8);
+  P.off_unreached = take(cur, (size_t)n * 4);
+  P.off_pos = take(cur, (size_t)n * 4);
+  P.off_in_off = take(cur, (size_t)(n + 1) * 4);
+  P.off_in_src = take(cur, (size_t)n * k * 4);
+  P.off_in_w = take(cur, (size_t)n * k * 4);
+  P.off_counts = take(cur, (size_t)n * 4);
+  // a partition holds at most n nodes
+  P.slots = n < PATH_SLOTS ? n : PATH_SLOTS;
+  P.slot_len = n;
+  P.off_sp_dist = take(cur, (size_t)P.slots * P.slot_len * 8);
+  P.off_sp_cur = take(cur, (size_t)P.slots * P.slot_len * 4);
+  P.off_sp_next = take(cur, (size_t)P.slots * P.slot_len * 4);
+  P.off_sp_inq = take(cur, (size_t)P.slots * P.slot_len * 4);
   P.total = cur;
   return P;
 }
@@ -1173,7 +1192,7 @@ knng_status knng_get_rows(const knng_graph* g, int64_t first, int64_t count, voi
 
 size_t knng_partition_scratch_bytes(const knng_graph* g, int32_t p) {
   if (!g || p < 1 || p > 64) return 0;
-  return part_scratch(g->n, p).total;
+  return part_scratch(g->n, p, g->S.k).total;
 }
 
 knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_num,
@@ -1191,7 +1210,7 @@ knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_
   if ((s = check_ptr(part_dev, "part_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(medoids_dev, "medoids_dev")) != KNNG_OK) return s;
   if ((uintptr_t)scratch_dev % ALIGN) return fail(KNNG_EINVAL, "scratch must be 256-byte aligned");
-  const PartScratch P = part_scratch(g->n, p);
+  const PartScratch P = part_scratch(g->n, p, g->S.k);
   if (scratch_bytes < P.total)
     return fail(KNNG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, P.total);
   const StorageLayout& S = g->S;
@@ -1212,10 +1231,27 @@ knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_
   a.members = reinterpret_cast<int32_t*>(sc + P.off_members);
   a.offsets = reinterpret_cast<int32_t*>(sc + P.off_offsets);
   a.sums = reinterpret_cast<double*>(sc + P.off_sums);
+  a.unreached = reinterpret_cast<int32_t*>(sc + P.off_unreached);
   a.is_float = S.is_float ? 1 : 0;
+  a.nbr_ids = at<int32_t>(g->st, S.off_ids);
+  a.nbr_d = at<int32_t>(g->st, S.off_dist);
+  a.k = S.k;
+  a.k_pad = S.k_pad;
+  a.pos = reinterpret_cast<int32_t*>(sc + P.off_pos);
+  a.in_off = reinterpret_cast<int32_t*>(sc + P.off_in_off);
+  a.in_src = reinterpret_cast<int32_t*>(sc + P.off_in_src);
+  a.in_w = reinterpret_cast<int32_t*>(sc + P.off_in_w);
+  a.sp_dist = reinterpret_cast<uint64_t*>(sc + P.off_sp_dist);
+  a.sp_cur = reinterpret_cast<int32_t*>(sc + P.off_sp_cur);
+  a.sp_next = reinterpret_cast<int32_t*>(sc + P.off_sp_next);
+  a.sp_inq = reinterpret_cast<int32_t*>(sc + P.off_sp_inq);
+  a.slots = (int32_t)P.slots;
+  a.slot_len = P.slot_len;
   int32_t init[64];
   initial_medoids(g->n, p, seed, init);
   KNNG_TRY(launch_set_medoids(medoids_dev, init, p, stream), "medoids launch");
+  KNNG_TRY(launch_in_edges(a, reinterpret_cast<int32_t*>(sc + P.off_counts), stream),
+           "in-edges launch");
   for (int it = 0; it < iters; ++it)
     KNNG_TRY(launch_partition_iteration(a, stream), "partition launch");
   return ok();

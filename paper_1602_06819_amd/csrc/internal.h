@@ -170,8 +170,18 @@ struct PartitionArgs {
   int32_t* part;                // [n]
   int32_t* members;             // [n] node ids grouped by partition, ascending
   int32_t* offsets;             // [p + 1]
-  double* sums;                 // [n] sum of distances to the own partition
+  double* sums;                 // [n] sum of path lengths to the reached members
+  int32_t* unreached;           // [n] members of the own partition not reached
   int is_float;
+  // the graph, taken as undirected: stored lists (out-edges) and in-edges
+  const int32_t* nbr_ids; const int32_t* nbr_d; int k, k_pad;
+  const int32_t* in_off;        // [n + 1] in-edge offsets
+  const int32_t* in_src;        // [n k] source of each in-edge
+  const int32_t* in_w;          // [n k] its stored distance bits
+  int32_t* pos;                 // [n] index of a node within its partition's members
+  // per-slot shortest-path scratch (one wavefront per slot, slot_len entries)
+  uint64_t* sp_dist; int32_t* sp_cur; int32_t* sp_next; int32_t* sp_inq;
+  int32_t slots; int64_t slot_len;
 };
 
 struct PeerArgs {
@@ -235,6 +245,7 @@ hipError_t launch_search(const SearchArgs& a, hipStream_t s);
 hipError_t launch_search_gnns(const SearchArgs& a, hipStream_t s);
 hipError_t launch_search_part(const SearchArgs& a, hipStream_t s);
 hipError_t launch_partition_iteration(const PartitionArgs& a, hipStream_t s);
+hipError_t launch_in_edges(const PartitionArgs& a, int32_t* counts, hipStream_t s);
 hipError_t launch_set_medoids(int32_t* medoids, const int32_t* host_ids, int p, hipStream_t s);
 hipError_t launch_part_budgets(const int32_t* part, int32_t n, int32_t p, int k, int speedup,
                                int32_t* counts, int32_t* budgets, hipStream_t s);

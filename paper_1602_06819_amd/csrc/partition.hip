@@ -12,10 +12,21 @@
 //                    lane m holds medoid m, the distance rows are staged
 //                    through LDS 64 nodes at a time with the next block's
 //                    loads in flight.
-//   k_members        each partition's nodes in ascending id order
-//   k_member_sums    per node, the sum of its distances to its partition
-//   k_medoid_argmin  per partition, the member with the smallest sum (ties:
-//                    smaller id) becomes the medoid
+//   k_members        each partition's nodes in ascending id order, and
+//                    each node's index among them
+//   k_member_paths   per node, shortest paths (Section 6) to the members of
+//                    its partition through the partition's nodes, over the
+//                    k-nn graph taken as undirected (a node's list and the
+//                    nodes whose lists hold it; edge length = the stored
+//                    distance): the members it does not reach and the sum of
+//                    its path lengths to the others
+//   k_medoid_argmin  per partition, the member with the fewest unreached
+//                    members, then the smallest sum (ties: smaller id),
+//                    becomes the medoid
+//
+// The in-edges are gathered once per partitioning (k_in_degree,
+// k_scan_offsets, k_in_fill); their order does not matter (shortest path
+// lengths do not depend on the order of relaxations).
 #include "common.h"
 #include "device.h"
 #include "eval.h"
@@ -125,65 +136,183 @@ __global__ __launch_bounds__(64) void k_assign(PartitionArgs a) {
 
 __global__ __launch_bounds__(64) void k_members(PartitionArgs a) {
   const int32_t m = blockIdx.x;
-  int32_t at = a.offsets[m];
+  const int32_t first = a.offsets[m];
+  int32_t at = first;
   for (int32_t u0 = 0; u0 < a.n; u0 += WAVE) {
     const int32_t u = u0 + (int32_t)threadIdx.x;
     const bool mine = u < a.n && a.part[u] == m;
     const uint64_t b = ballot(mine);
-    if (mine) a.members[at + rank_below(b)] = u;
+    if (mine) {
+      const int32_t j = at + rank_below(b);
+      a.members[j] = u;
+      a.pos[u] = j - first;
+    }
     at += __popcll(b);
   }
 }
 
-template <class Eval>
-__global__ __launch_bounds__(64) void k_member_sums(PartitionArgs a) {
-  const int32_t u = blockIdx.x;
-  const int32_t m = a.part[u];
-  const int32_t lo = a.offsets[m], hi = a.offsets[m + 1];
-  Eval ev;
-  ev.load(a.vec, a.row_bytes, a.dim, u);
-  double fs = 0.0;
-  int64_t is = 0;
-  for (int32_t j0 = lo; j0 < hi; j0 += WAVE) {
-    const int32_t j = j0 + (int32_t)threadIdx.x;
-    const bool ok = j < hi;
-    const int32_t v = ok ? a.members[j] : 0;
-    const int cnt = hi - j0 < WAVE ? hi - j0 : WAVE;
-    const uint32_t d = ev.dist(a.vec, a.row_bytes, v, ok, cnt);
-    if (ok) {
-      if (a.is_float)
-        fs += (double)__uint_as_float(d);
-      else
-        is += (int64_t)d;
-    }
-  }
+// ---- in-edges of the k-nn graph -------------------------------------------------
+__global__ void k_in_degree(PartitionArgs a, int32_t* counts) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.n * a.k) return;
+  const int64_t u = e / a.k;
+  const int32_t v = a.nbr_ids[u * a.k_pad + (e - u * a.k)];
+  if (v >= 0 && v < a.n) atomicAdd(&counts[v], 1);
+}
+
+// exclusive prefix sums of counts[0 .. n) into off[0 .. n], one workgroup
+__global__ __launch_bounds__(1024) void k_scan_offsets(const int32_t* counts, int32_t n,
+                                                       int32_t* off) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry;
+  const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int32_t base = 0; base < n; base += 1024) {
+    const int32_t i = base + t;
+    const int32_t c = i < n ? counts[i] : 0;
+    int32_t incl = c;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    fs += __shfl_xor(fs, off, WAVE);
-    is += (int64_t)shfl_xor_u64((uint64_t)is, off);
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int32_t x = __shfl_up(incl, o, WAVE);
+      if (lane >= o) incl += x;
+    }
+    if (lane == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    int32_t before = carry;
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    if (i < n) off[i] = before + incl - c;
+    __syncthreads();
+    if (t == 1023) carry = before + incl;
+    __syncthreads();
   }
-  if (threadIdx.x == 0) a.sums[u] = a.is_float ? fs : (double)is;
+  if (t == 0) off[n] = carry;
+}
+
+__global__ void k_in_fill(PartitionArgs a, int32_t* cursor, int32_t* src, int32_t* w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.n * a.k) return;
+  const int64_t u = e / a.k;
+  const int64_t at = u * a.k_pad + (e - u * a.k);
+  const int32_t v = a.nbr_ids[at];
+  if (v < 0 || v >= a.n) return;
+  const int32_t slot = a.in_off[v] + atomicAdd(&cursor[v], 1);
+  src[slot] = (int32_t)u;
+  w[slot] = a.nbr_d[at];
+}
+
+// ---- shortest paths within a partition (Section 6) ------------------------------
+// One wavefront per source node, in a scratch slot of its own: a worklist
+// Bellman-Ford over the partition's nodes (lengths are non-negative, so the
+// lengths settle within as many rounds as the partition has members; the
+// loop is bounded by that).  Lengths are exact int64 sums of the stored
+// distances (uint8 graphs) or float64 sums of the float32 ones, kept as
+// 64-bit patterns that order like the values; UNREACHED marks a member not
+// (yet) reached.  Lane 0 then sums the lengths in member order.
+constexpr uint64_t UNREACHED = ~0ull;
+
+__global__ __launch_bounds__(64) void k_member_paths(PartitionArgs a) {
+  const int lane = threadIdx.x;
+  uint64_t* dist = a.sp_dist + (int64_t)blockIdx.x * a.slot_len;
+  int32_t* cur = a.sp_cur + (int64_t)blockIdx.x * a.slot_len;
+  int32_t* nxt = a.sp_next + (int64_t)blockIdx.x * a.slot_len;
+  int32_t* inq = a.sp_inq + (int64_t)blockIdx.x * a.slot_len;
+  __shared__ int32_t s_next;
+  for (int32_t u = blockIdx.x; u < a.n; u += gridDim.x) {
+    const int32_t t = a.part[u];
+    const int32_t lo = a.offsets[t];
+    const int32_t nt = a.offsets[t + 1] - lo;
+    for (int32_t l = lane; l < nt; l += WAVE) {
+      dist[l] = UNREACHED;
+      inq[l] = 0;
+    }
+    __threadfence();
+    __syncthreads();
+    if (lane == 0) {
+      dist[a.pos[u]] = 0ull;
+      cur[0] = a.pos[u];
+    }
+    __threadfence();
+    __syncthreads();
+    int32_t ncur = 1;
+    for (int32_t round = 0; ncur > 0 && round <= nt; ++round) {
+      if (lane == 0) s_next = 0;
+      for (int32_t i = lane; i < ncur; i += WAVE) inq[cur[i]] = 0;
+      __threadfence();
+      __syncthreads();
+      for (int32_t i = lane; i < ncur; i += WAVE) {
+        const int32_t lx = cur[i];
+        const int32_t x = a.members[lo + lx];
+        const uint64_t dx = dist[lx];
+        auto relax = [&](int32_t y, int32_t wbits) {
+          if (y < 0 || a.part[y] != t) return;
+          const int32_t ly = a.pos[y];
+          uint64_t nd;
+          if (a.is_float)
+            nd = (uint64_t)__double_as_longlong(__longlong_as_double((long long)dx) +
+                                                (double)__int_as_float(wbits));
+          else
+            nd = dx + (uint64_t)(uint32_t)wbits;
+          const uint64_t old = atomicMin((unsigned long long*)&dist[ly], (unsigned long long)nd);
+          if (nd < old && atomicExch(&inq[ly], 1) == 0) nxt[atomicAdd(&s_next, 1)] = ly;
+        };
+        for (int j = 0; j < a.k; ++j)
+          relax(a.nbr_ids[(int64_t)x * a.k_pad + j], a.nbr_d[(int64_t)x * a.k_pad + j]);
+        for (int32_t e = a.in_off[x]; e < a.in_off[x + 1]; ++e) relax(a.in_src[e], a.in_w[e]);
+      }
+      __threadfence();
+      __syncthreads();
+      ncur = s_next;
+      int32_t* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+      __syncthreads();
+    }
+    if (lane == 0) {
+      int32_t missed = 0;
+      double fs = 0.0;
+      uint64_t is = 0;
+      for (int32_t l = 0; l < nt; ++l) {
+        const uint64_t v = dist[l];
+        if (v == UNREACHED)
+          ++missed;
+        else if (a.is_float)
+          fs += __longlong_as_double((long long)v);
+        else
+          is += v;
+      }
+      a.sums[u] = a.is_float ? fs : (double)is;
+      a.unreached[u] = missed;
+    }
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(64) void k_medoid_argmin(PartitionArgs a) {
   const int32_t m = blockIdx.x;
   const int32_t lo = a.offsets[m], hi = a.offsets[m + 1];
   if (hi <= lo) return;                    // empty partition keeps its medoid
+  int32_t bm = 0x7fffffff;                 // (unreached, sum, id), smallest first
   double bs = 1e308;
   int32_t bu = 0x7fffffff;
+  auto less = [](int32_t m1, double s1, int32_t u1, int32_t m2, double s2, int32_t u2) {
+    return m1 < m2 || (m1 == m2 && (s1 < s2 || (s1 == s2 && u1 < u2)));
+  };
   for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += WAVE) {
     const int32_t u = a.members[j];
-    const double s = a.sums[u];
-    if (s < bs || (s == bs && u < bu)) {
-      bs = s;
+    if (less(a.unreached[u], a.sums[u], u, bm, bs, bu)) {
+      bm = a.unreached[u];
+      bs = a.sums[u];
       bu = u;
     }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
+    const int32_t om = __shfl_xor(bm, off, WAVE);
     const double os = __shfl_xor(bs, off, WAVE);
     const int32_t ou = __shfl_xor(bu, off, WAVE);
-    if (os < bs || (os == bs && ou < bu)) {
+    if (less(om, os, ou, bm, bs, bu)) {
+      bm = om;
       bs = os;
       bu = ou;
     }
@@ -195,13 +324,6 @@ template <class Eval>
 struct DistFn {
   static hipError_t go(const PartitionArgs& a, hipStream_t s, dim3 grid, size_t) {
     hipLaunchKernelGGL((k_medoid_dist<Eval>), grid, dim3(64), 0, s, a);
-    return hipGetLastError();
-  }
-};
-template <class Eval>
-struct SumFn {
-  static hipError_t go(const PartitionArgs& a, hipStream_t s, dim3 grid, size_t) {
-    hipLaunchKernelGGL((k_member_sums<Eval>), grid, dim3(64), 0, s, a);
     return hipGetLastError();
   }
 };
@@ -223,10 +345,29 @@ hipError_t launch_partition_iteration(const PartitionArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_members, dim3((unsigned)a.p), dim3(64), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = dispatch_eval<SumFn>(a.format, a.row_bytes, a, s, dim3((unsigned)a.n), 0)) !=
-      hipSuccess)
-    return e;
+  if (a.slots < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_member_paths, dim3((unsigned)a.slots), dim3(64), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_medoid_argmin, dim3((unsigned)a.p), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// In-edge lists (in_off, in_src, in_w) of the graph's n nodes; `counts` is
+// [n] scratch, also used as the fill cursor.
+hipError_t launch_in_edges(const PartitionArgs& a, int32_t* counts, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipError_t e;
+  if ((e = launch_fill_i32(counts, a.n, 0, s)) != hipSuccess) return e;
+  const int64_t edges = (int64_t)a.n * a.k;
+  const unsigned blocks = (unsigned)((edges + 255) / 256);
+  hipLaunchKernelGGL(k_in_degree, dim3(blocks), dim3(256), 0, s, a, counts);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, counts, a.n,
+                     const_cast<int32_t*>(a.in_off));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_fill_i32(counts, a.n, 0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_in_fill, dim3(blocks), dim3(256), 0, s, a, counts,
+                     const_cast<int32_t*>(a.in_src), const_cast<int32_t*>(a.in_w));
   return hipGetLastError();
 }
 

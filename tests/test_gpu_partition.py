@@ -41,7 +41,9 @@ def test_partition_bit_exact(G, n, dim, p, iters, imb):
     g = G.KnnGraph.build_exact(cfg, tensor(X))
     say(f"partition n={n} p={p} iters={iters} imbalance={imb}")
     part, med = g.partition(p, iters=iters, imbalance=imb, seed=77)
-    o_part, o_med = Pt.balanced_kmedoids(X, p, iters, seed=77, imb_num=imb[0], imb_den=imb[1])
+    oi, od = O.exact_graph(X, 10)
+    o_part, o_med = Pt.balanced_kmedoids(X, oi, od, p, iters, seed=77, imb_num=imb[0],
+                                         imb_den=imb[1])
     assert np.array_equal(part.cpu().numpy(), o_part)
     assert med.cpu().numpy().tolist() == o_med
 
@@ -53,11 +55,38 @@ def test_partition_float_agrees(G):
     cfg = G.GraphConfig(dim=dim, k=10, capacity=n, max_batch=16, dtype="f32", score="exact")
     g = G.KnnGraph.build_exact(cfg, tensor(X))
     part, med = g.partition(p, iters=3, seed=5)
-    o_part, o_med = Pt.balanced_kmedoids(X, p, 3, seed=5)
+    # the oracle on the graph's own stored lists (float32 lengths): its
+    # assignments may differ at near ties of the float64 distances
+    gi, gd = (t.cpu().numpy() for t in g.lists())
+    o_part, o_med = Pt.balanced_kmedoids(X, gi, gd, p, 3, seed=5)
     agree = float(np.mean(part.cpu().numpy() == o_part))
     say(f"  float partition agreement {agree:.4f}")
     assert agree > 0.98
     assert np.bincount(part.cpu().numpy(), minlength=p).tolist() == [n // p] * p
+
+
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_medoid_update_by_graph_paths(G, kind):
+    """One iteration from given medoids: the assignment, then the medoids the
+    update step computes from shortest paths in the graph, against the
+    oracle's Dijkstra on the same stored lists (the float32 lengths summed in
+    float64 in the same order: equal bits)."""
+    from datagen import float_mixture
+    n, dim, k, p = 1800, 12, 8, 5
+    if kind == "u8":
+        X = u8_points(93, n, dim, clusters=5, sigma=14.0)
+        cfg = G.GraphConfig(dim=dim, k=k, capacity=n, max_batch=16)
+    else:
+        X = float_mixture(94, 5, dim).sample(n, 1094).astype(np.float32)
+        cfg = G.GraphConfig(dim=dim, k=k, capacity=n, max_batch=16, dtype="f32",
+                            score="exact")
+    g = G.KnnGraph.build_exact(cfg, tensor(X))
+    part, med = g.partition(p, iters=1, seed=21)
+    gi, gd = (t.cpu().numpy() for t in g.lists())
+    pn = part.cpu().numpy()
+    o_med = Pt.update(gi, gd, pn, Pt.initial_medoids(n, p, 21))
+    say(f"medoids by graph paths {kind}: {med.cpu().numpy().tolist()}")
+    assert med.cpu().numpy().tolist() == o_med
 
 
 @pytest.mark.parametrize("p,speedup", [(4, 6), (1, 8), (8, 3), (4, 1)])

@@ -190,6 +190,7 @@ def main(argv=None):
     ap.add_argument("--queries", type=int, default=100)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--speedup", type=int, default=None)
+    ap.add_argument("--parts", default="1,2,4,8,16,32", help="partitions experiment: part counts")
     ap.add_argument("--e", type=float, default=5.0)
     ap.add_argument("--batch", type=int, default=1)
     args = ap.parse_args(argv)
@@ -202,7 +203,7 @@ def main(argv=None):
                       [1, 2, 4, 8, 16, 32, 64, 128], args.reps)
     elif args.experiment == "partitions":
         it = run_partitions(w, args.n or 8000, args.queries, args.speedup or 4,
-                            [1, 2, 4, 8, 16, 32], args.reps)
+                            [int(v) for v in args.parts.split(",")], args.reps)
     elif args.experiment == "depth":
         it = run_depth(w, args.n or 1000, args.n_add or 1000, args.speedup or 20, [1, 2, 3, 4, 5])
     else:

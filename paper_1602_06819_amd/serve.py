@@ -11,6 +11,8 @@ later request overtakes it).  The epoch's queries and inserts then run as
 one ``knng_epoch`` against the snapshot before the epoch, so a query's
 answer and an insert's effect are those of running the epoch's requests
 alone on that snapshot.  A request completes when its epoch completes.
+The host waits on epochs' completion events, never on the device, and
+can keep more than one epoch enqueued (``inflight``).
 
 Time is the server's wall clock, except that idle gaps (no request has
 arrived) are skipped instead of slept: GPU work is unaffected by them, and
@@ -159,68 +161,125 @@ class ServeResult:
 
 
 def serve(graph, reqs: list[Request], ins_points, q_points, max_query_points: int,
-          keep_queries: bool = False, sync=None) -> ServeResult:
+          keep_queries: bool = False, inflight: int = 1) -> ServeResult:
     """Run the requests through `graph` (a KnnGraph).  `ins_points` and
-    `q_points` are device tensors holding the insert and query streams."""
+    `q_points` are device tensors holding the insert and query streams.
+
+    Up to `inflight` epochs are enqueued at once: with 2 or more, while the
+    GPU runs one, the host admits the requests that have arrived and
+    enqueues the next behind it on the stream (stream order keeps each
+    epoch on the snapshot its predecessors leave).  The host never
+    synchronises the device; it waits on the oldest epoch's completion
+    event when the pipeline is full or nothing else can be admitted.  An
+    epoch completes, and with it its requests, when its event does.  With
+    1 (the default), the next epoch is formed when the previous one ends,
+    so it takes every request that arrived meanwhile: on the serving
+    workload an epoch's time hardly depends on its size, and a second
+    queued epoch only delays the requests that arrive after it was formed
+    (measured: p50/p99 103/279 ms against 170/354 ms at the same
+    throughput, 120 requests/s)."""
     import torch
-    sync = sync or torch.cuda.synchronize
+    if inflight < 1:
+        raise ValueError("inflight must be >= 1")
     adm = Admission(graph.cfg.max_batch, max_query_points)
     for r in reqs:
         if not adm.fits_alone(r):
             raise ValueError(f"request {r.rid} ({r.kind}, {r.size} points) exceeds the limits")
     pending = deque(sorted(reqs, key=lambda r: r.arrival))
     res = ServeResult()
+    flight: deque = deque()
     skipped = 0.0                 # idle time jumped over
-    sync()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
 
     def now() -> float:
         return time.perf_counter() - t0 + skipped
 
-    while pending:
-        t = now()
-        if pending[0].arrival > t:
-            skipped += pending[0].arrival - t        # idle: jump to the next arrival
-            t = now()
-        ep = plan_epoch(adm.take(pending, t))
-        ep.start = t
-        ep.n_before = graph.n
-        x = ins_points[ep.ins_lo:ep.ins_hi] if ep.ins_hi > ep.ins_lo else None
-        q = q_points[ep.q_lo:ep.q_hi] if ep.q_hi > ep.q_lo else None
-        _, _, qi, qd, _ = graph.epoch(x, q)
-        sync()
+    def retire() -> None:
+        ep, start, stop, qi, qd = flight.popleft()
+        stop.synchronize()
         ep.end = now()
-        res.busy += ep.end - ep.start
+        res.busy += start.elapsed_time(stop) / 1000.0
         for r in ep.requests:
             res.latency[r.rid] = ep.end - r.arrival
         if keep_queries:
             res.query_out.append(None if qi is None else (qi.cpu().numpy(), qd.cpu().numpy()))
         res.epochs.append(ep)
+
+    while pending or flight:
+        t = now()
+        if pending and pending[0].arrival <= t and len(flight) < inflight:
+            ep = plan_epoch(adm.take(pending, t))
+            ep.start = t
+            ep.n_before = graph.n
+            x = ins_points[ep.ins_lo:ep.ins_hi] if ep.ins_hi > ep.ins_lo else None
+            q = q_points[ep.q_lo:ep.q_hi] if ep.q_hi > ep.q_lo else None
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            start.record()
+            _, _, qi, qd, _ = graph.epoch(x, q)
+            stop.record()
+            flight.append((ep, start, stop, qi, qd))
+        elif flight and len(flight) < inflight and pending:
+            # room in the pipeline: the oldest epoch's end or the next
+            # arrival, whichever comes first
+            stop = flight[0][2]
+            while not stop.query() and pending[0].arrival > now():
+                time.sleep(0.0001)
+            if stop.query():
+                retire()
+        elif flight:
+            retire()
+        else:
+            skipped += pending[0].arrival - t        # idle: jump to the next arrival
     first = min(r.arrival for r in reqs)
     res.span = max(ep.end for ep in res.epochs) - first
     return res
 
 
+def requests_for_inserts(seed: int, rate: float, inserts: int, **kw) -> list[Request]:
+    """The shortest prefix of the request stream whose inserts reach
+    `inserts` points (the stream's sizes do not depend on the rate)."""
+    count = 256
+    while True:
+        reqs = make_requests(seed, rate, count, **kw)
+        total = 0
+        for i, r in enumerate(reqs):
+            if r.kind == "insert":
+                total += r.size
+                if total >= inserts:
+                    return reqs[:i + 1]
+        count *= 2
+
+
 def main(argv=None) -> None:
-    """Offered-load sweep of the serving workload: one JSON line per rate."""
+    """Offered-load sweep of the serving workload: one JSON line per rate,
+    each growing the graph from its initial size by the same request stream;
+    with --recall, recall@k of each served graph against the exact graph of
+    all its points."""
     import argparse
     import json
     import sys
 
+    import numpy as np
     import torch
 
     from datagen import get_workload
+    from . import metrics
     from .graph import GraphConfig, KnnGraph
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="serve-f32-d96-1m-2m")
-    ap.add_argument("--rates", default="100,200,400", help="requests per second")
-    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--rates", default="60,120,180", help="requests per second")
+    ap.add_argument("--inserts", type=int, default=1_000_000,
+                    help="serve requests until this many points are inserted")
     ap.add_argument("--max-batch", type=int, default=16384)
     ap.add_argument("--max-query", type=int, default=4096)
+    ap.add_argument("--inflight", type=int, default=1, help="epochs enqueued at once")
     ap.add_argument("--speedup", type=int, default=None)
     ap.add_argument("--expansion", default=None)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--recall", action="store_true")
     args = ap.parse_args(argv)
     w = get_workload(args.workload)
     if args.expansion:
@@ -228,7 +287,7 @@ def main(argv=None) -> None:
         w = w.scaled(expansion_num=num, expansion_den=den)
     speedup = args.speedup or w.speedup
     rates = [float(r) for r in args.rates.split(",")]
-    plans = {r: make_requests(args.seed, r, args.requests) for r in rates}
+    plans = {r: requests_for_inserts(args.seed, r, args.inserts) for r in rates}
     need_ins = max(stream_totals(p)[0] for p in plans.values())
     need_q = max(stream_totals(p)[1] for p in plans.values())
     n0 = w.n_initial
@@ -250,12 +309,26 @@ def main(argv=None) -> None:
           file=sys.stderr, flush=True)
     g0.close()
     del g0
+    exact = {}
     for r in rates:
         g = KnnGraph.load(cfg, Xd[:n0], ids, d)
-        res = serve(g, plans[r], Xd[n0:], Qd, args.max_query)
-        out = {"workload": w.name, "offered_rate_req_s": r, "speedup": speedup,
-               "expansion": f"{w.expansion_num}/{w.expansion_den}", "n_final": g.n,
-               **res.summary(plans[r])}
+        res = serve(g, plans[r], Xd[n0:], Qd, args.max_query, inflight=args.inflight)
+        n = g.n
+        out = {"workload": w.name, "offered_rate_req_s": r, "inflight": args.inflight,
+               "speedup": speedup, "expansion": f"{w.expansion_num}/{w.expansion_den}",
+               "depth": w.depth, "n_final": n, **res.summary(plans[r])}
+        if args.recall:
+            if n not in exact:
+                cx = GraphConfig(dim=w.dim, k=w.k, capacity=n, max_batch=1024,
+                                 dtype=cfg.dtype, score="exact")
+                gx = KnnGraph.build_exact(cx, Xd[:n])
+                exact[n] = gx.lists()[0].cpu().numpy()
+                gx.close()
+                del gx
+            io = g.lists()[0].cpu().numpy()
+            ie = exact[n]
+            out["recall_at_k"] = metrics.recall(io, ie)
+            out["recall_new_nodes"] = metrics.recall(io[n0:], ie[n0:])
         print(json.dumps(out), flush=True)
         g.close()
         del g

@@ -64,3 +64,16 @@ def test_admission_query_limit_blocks_head():
     pending = deque(reqs)
     assert [r.rid for r in adm.take(pending, 0.0)] == [0]
     assert [r.rid for r in adm.take(pending, 0.0)] == [1, 2]
+
+
+def test_requests_for_inserts_is_the_shortest_prefix():
+    from paper_1602_06819_amd.serve import requests_for_inserts
+    for rate in (10.0, 500.0):
+        reqs = requests_for_inserts(3, rate, 20_000)
+        ins = [r.size for r in reqs if r.kind == "insert"]
+        assert sum(ins) >= 20_000 and sum(ins) - ins[-1] < 20_000
+        assert reqs[-1].kind == "insert"
+    # the stream's kinds and sizes do not depend on the rate
+    a = requests_for_inserts(3, 10.0, 20_000)
+    b = requests_for_inserts(3, 500.0, 20_000)
+    assert [(r.kind, r.size) for r in a] == [(r.kind, r.size) for r in b]

@@ -107,7 +107,9 @@ def search_algorithmic_bytes(score: str, dim: int, k: int, points: int, evals: f
     v_bytes = {"u8": dim, "bf16": 2 * dim, "bf16m": 2 * dim + 4, "fp8": dim + 4,
                "exact": 4 * dim}[score]
     q_bytes = 4 * dim if is_float else dim
-    keep = min(64, 2 * k) if score in ("bf16", "bf16m", "fp8") else k
+    # candidates the reduced-precision scores keep for the float32 re-rank
+    mult = {"bf16": 2, "bf16m": 2, "fp8": 4}.get(score, 1)
+    keep = min(mult * k, 128 if k > 16 else 64) if mult > 1 else k
     total = evals * v_bytes + lists * k * 4 + points * (q_bytes + k * 8)
     if is_float:
         total += points * keep * 4 * dim

@@ -95,10 +95,11 @@ typedef enum { KNNG_METRIC_L2 = 0, KNNG_METRIC_COSINE = 1 } knng_metric;
  *             bfloat16 matrix cores as |q|^2 - 2 q.x + |x|^2 (dim <= 128;
  *             each row carries its squared norm); KNNG_SCORE_FP8 E4M3 codes
  *             with a per-row scale (rows above 256 coordinates on the FP8
- *             matrix cores).  Reduced-precision scores keep
- *             min(2k, 64) candidates and re-rank them by the float32
- *             distance; every stored distance is float32.  KNNG_U8
- *             requires KNNG_SCORE_EXACT.
+ *             matrix cores).  Reduced-precision scores keep 2k
+ *             (bfloat16) or 4k (FP8) candidates, at most 128 (at most 64
+ *             for k <= 16), and re-rank them by the float32 distance;
+ *             every stored distance is float32.  KNNG_U8 requires
+ *             KNNG_SCORE_EXACT.
  *  capacity   largest number of nodes the graph may ever hold (< 2^31).
  *  max_batch  largest batch (insert) or query count per call.
  *  speedup    iGNNS budget: B(n) = min(n, max(k, ceil(n / speedup)))

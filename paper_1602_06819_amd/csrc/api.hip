@@ -373,8 +373,14 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.nbr_ids = at<int32_t>(g->st, S.off_ids);
   a.k = S.k;
   a.k_pad = S.k_pad;
-  // BF16 / FP8 scoring keeps twice as many candidates for the float32 re-rank
-  a.keep = (S.format == ROW_BF16 || S.format == ROW_FP8) ? (2 * S.k < 64 ? 2 * S.k : 64) : S.k;
+  // reduced-precision scores keep more candidates for the float32 re-rank:
+  // 2k for bfloat16 (8 significant bits), 4k for FP8 E4M3 (4), at most 128
+  // (lists of up to 16 ids: at most 64)
+  {
+    const int mult = S.format == ROW_FP8 ? 4 : S.format == ROW_BF16 ? 2 : 1;
+    const int cap = S.k_pad > 16 ? 128 : 64;
+    a.keep = mult * S.k < cap ? mult * S.k : cap;
+  }
   a.n = (int32_t)g->n;
   a.B = (int32_t)budget(g->n, S.k, g->p.speedup);
   a.m_mod = modulus_for(g->n);

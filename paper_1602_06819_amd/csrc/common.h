@@ -141,6 +141,60 @@ __device__ __forceinline__ void lanes_topk_offer_ranked(uint64_t& mine, bool fla
   __syncthreads();
 }
 
+// A list of up to 2 * WAVE entries in two registers per lane: lane j holds
+// the entries of ranks j (`lo`) and WAVE + j (`hi`).  Offer the flagged keys
+// of the lanes: every qualifying candidate and every list entry computes
+// its rank in the union by counting smaller keys (LDS broadcast reads), and
+// the k smallest are scattered into place.  `cbuf` is a WAVE-entry and
+// `rbuf`, `obuf` are 2 * WAVE-entry LDS arrays of this wavefront (a
+// workgroup of one wavefront).
+__device__ __forceinline__ void wave_topk_offer_ranked2(uint64_t& lo, uint64_t& hi, bool flag,
+                                                        uint64_t key, int k, uint64_t* cbuf,
+                                                        uint64_t* rbuf, uint64_t* obuf) {
+  const int lane = lane_id();
+  const uint64_t kth = k <= WAVE ? readlane_u64(lo, k - 1) : readlane_u64(hi, k - 1 - WAVE);
+  const bool pass = flag && key < kth;
+  const uint64_t P = ballot(pass);
+  const int np = __popcll(P);
+  if (np == 0) return;
+  if (pass) cbuf[rank_below(P)] = key;
+  rbuf[lane] = lo;
+  rbuf[WAVE + lane] = hi;
+  obuf[lane] = KEY_INF;
+  obuf[WAVE + lane] = KEY_INF;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  int pos = 2 * WAVE;
+  if (pass) {
+    int r = 0;
+    for (int t = 0; t < k; ++t) r += rbuf[t] < key;
+    for (int t = 0; t < np; ++t) r += cbuf[t] < key;
+    pos = r;
+  }
+  int rlo = 2 * WAVE, rhi = 2 * WAVE;
+  if (lane < k && lo != KEY_INF) {
+    int r = lane;
+    for (int t = 0; t < np; ++t) r += cbuf[t] < lo;
+    rlo = r;
+  }
+  if (WAVE + lane < k && hi != KEY_INF) {
+    int r = WAVE + lane;
+    for (int t = 0; t < np; ++t) r += cbuf[t] < hi;
+    rhi = r;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (pos < k) obuf[pos] = key;
+  if (rlo < k) obuf[rlo] = lo;
+  if (rhi < k) obuf[rhi] = hi;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  lo = lane < k ? obuf[lane] : KEY_INF;
+  hi = WAVE + lane < k ? obuf[WAVE + lane] : KEY_INF;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // The same for a workgroup of exactly one wavefront: LDS accesses of one
 // wavefront complete in order, so wavefront-scope ordering suffices and no
 // workgroup barrier (which would also wait for outstanding global loads)

@@ -53,7 +53,7 @@ namespace knng {
 template <int G, int CPL>
 struct ScoreI8 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false, kWide = false;
   v4i q[CPL];
   int32_t qq;
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
@@ -131,7 +131,7 @@ __device__ __forceinline__ bool keep_f32(uint32_t d, uint32_t best, int num, int
 template <int G, int CPL>
 struct ScoreBF16 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false, kWide = true;
   float q[CPL][8];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 8>(a, r, qi, q);
@@ -159,7 +159,7 @@ struct ScoreBF16 {
 template <int G, int CPL>
 struct ScoreFP8 {
   static constexpr bool kSide = true;    // the row scale
-  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false, kWide = true;
   float q[CPL][16];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 16>(a, r, qi, q);
@@ -189,7 +189,7 @@ struct ScoreFP8 {
 template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kSide = false;
-  static constexpr bool kSide2 = false, kMfma = false, kBatch = false;
+  static constexpr bool kSide2 = false, kMfma = false, kBatch = false, kWide = false;
   float q[CPL][4];
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
@@ -225,7 +225,7 @@ struct ScoreF32 {
 template <int CPL>
 struct ScoreFP8M {
   static_assert(CPL % 2 == 0, "an MFMA step takes two 16-byte chunks per lane");
-  static constexpr bool kSide = true, kSide2 = true, kMfma = true, kBatch = false;
+  static constexpr bool kSide = true, kSide2 = true, kMfma = true, kBatch = false, kWide = true;
   static constexpr int G = 4;
   v4i qh[CPL], ql[CPL];
   float qq;                       // |q|^2
@@ -304,7 +304,7 @@ struct ScoreFP8M {
 // 0; it is valid in the candidates' sub-0 lanes 0-15.
 template <int CPL>
 struct ScoreBF16M {
-  static constexpr bool kSide = false, kSide2 = true, kMfma = true, kBatch = true;
+  static constexpr bool kSide = false, kSide2 = true, kMfma = true, kBatch = true, kWide = true;
   static constexpr int G = 4;
   v4i qa[CPL];                    // A operand: row 0 h, row 1 l, other rows 0
   float qq;                       // |q|^2
@@ -400,10 +400,10 @@ struct ScoreBF16M {
 // are never evaluated or counted, as if absent -- with that partition's
 // budget; the rows' results are merged afterwards (k_merge_partitions).
 template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB,
-          bool GNNS = false, bool PART = false>
+          bool GNNS = false, bool PART = false, bool K2 = false>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint64_t tk_c[WAVE], tk_r[WAVE], tk_o[WAVE];
+  __shared__ uint64_t tk_c[WAVE], tk_r[K2 ? 2 * WAVE : WAVE], tk_o[K2 ? 2 * WAVE : WAVE];
   static_assert(G % PB == 0, "pass groups must divide the passes");
   constexpr int NG = G / PB;                      // pass groups per step
   constexpr int NB = NG > 1 ? 2 : 1;              // register buffers
@@ -476,6 +476,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     }
 
     uint64_t rk = KEY_INF;          // result list: lane j < kk holds the j-th best
+    uint64_t rk2 = KEY_INF;         // K2: lane j holds the (WAVE + j)-th best
     uint64_t kth = KEY_INF;         // (uniform) the list's kk-th key
     uint32_t best = 0xffffffffu;    // (uniform) best distance bits so far
     const int kk = a.keep;          // entries kept (k, or more before a re-rank)
@@ -734,8 +735,13 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       }
       const uint64_t key = make_key(d_now, cid_now);
       if (ballot(mine && key < kth)) {
-        wave_topk_offer_ranked(rk, mine, key, kk, tk_c, tk_r, tk_o);
-        kth = readlane_u64(rk, kk - 1);
+        if (K2 && kk > WAVE) {
+          wave_topk_offer_ranked2(rk, rk2, mine, key, kk, tk_c, tk_r, tk_o);
+          kth = readlane_u64(rk2, kk - 1 - WAVE);
+        } else {
+          wave_topk_offer_ranked(rk, mine, key, kk, tk_c, tk_r, tk_o);
+          kth = readlane_u64(rk, kk - 1);
+        }
         best = key_dist(readlane_u64(rk, 0));
       }
       evals += __popcll(C);
@@ -752,8 +758,18 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       const uint32_t d32 =
           canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride, a.master_chunks, cid);
       const uint64_t nk = have ? make_key(d32, cid) : KEY_INF;
+      uint64_t nk2 = KEY_INF;
+      bool have2 = false;
+      if (K2 && kk > WAVE) {
+        have2 = WAVE + lane < kk && rk2 != KEY_INF;
+        const int32_t cid2 = have2 ? key_id(rk2) : -1;
+        const uint32_t e32 =
+            canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride, a.master_chunks, cid2);
+        nk2 = have2 ? make_key(e32, cid2) : KEY_INF;
+      }
       rk = KEY_INF;
       wave_topk_offer_ranked(rk, have, nk, a.k, tk_c, tk_r, tk_o);
+      if (K2 && kk > WAVE) wave_topk_offer_ranked(rk, have2, nk2, a.k, tk_c, tk_r, tk_o);
     }
     if (lane < R.out_stride) {
       const bool have = lane < a.k && rk != KEY_INF;
@@ -777,18 +793,23 @@ template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS 
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
   // KPADS: the list strides this instantiation serves (1: 16, 2: 32, 4: 64)
   const bool gvis = a.gvis != nullptr;
-#define KNNG_SEARCH_GO(LR, GV)                                                                 \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART>), dim3(grid), \
-                     dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
+  // lists of more than 16 ids with a re-ranked reduced-precision score keep
+  // up to 2 * WAVE candidates (two per lane)
+  constexpr bool W2 = Score::kWide && CCPL > 0;
+#define KNNG_SEARCH_GO(LR, GV, K2)                                                       \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART, K2>),   \
+                     dim3(grid), dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
+  if (a.keep > 2 * WAVE || (a.keep > WAVE && !(W2 && a.k_pad > 16)))
+    return hipErrorInvalidValue;
   if (a.k_pad == 16) {
     if constexpr ((KPADS & 1) != 0) {
-      if (gvis) KNNG_SEARCH_GO(16, true); else KNNG_SEARCH_GO(16, false);
+      if (gvis) KNNG_SEARCH_GO(16, true, false); else KNNG_SEARCH_GO(16, false, false);
     } else {
       return hipErrorInvalidValue;
     }
   } else if (a.k_pad == 32) {
     if constexpr ((KPADS & 2) != 0) {
-      if (gvis) KNNG_SEARCH_GO(32, true); else KNNG_SEARCH_GO(32, false);
+      if (gvis) KNNG_SEARCH_GO(32, true, W2); else KNNG_SEARCH_GO(32, false, W2);
     } else {
       return hipErrorInvalidValue;
     }
@@ -796,9 +817,9 @@ hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, si
     if constexpr ((KPADS & 4) == 0) {
       return hipErrorInvalidValue;
     } else if constexpr (PB < G) {
-      if (gvis) KNNG_SEARCH_GO(64, true); else KNNG_SEARCH_GO(64, false);
+      if (gvis) KNNG_SEARCH_GO(64, true, W2); else KNNG_SEARCH_GO(64, false, W2);
     } else {
-      if (gvis) KNNG_SEARCH_GO(0, true); else KNNG_SEARCH_GO(0, false);
+      if (gvis) KNNG_SEARCH_GO(0, true, W2); else KNNG_SEARCH_GO(0, false, W2);
     }
   }
 #undef KNNG_SEARCH_GO

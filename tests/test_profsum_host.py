@@ -104,7 +104,8 @@ def test_search_algorithmic_bytes():
     b = bench.search_algorithmic_bytes("bf16", 128, 20, 1, 100.0, 10.0)
     assert b == pytest.approx(100 * 256 + 10 * 80 + 512 + 160 + 40 * 512)
     b = bench.search_algorithmic_bytes("fp8", 960, 50, 1, 1.0, 0.0)
-    assert b == pytest.approx(964 + 3840 + 400 + 64 * 3840)
+    # FP8 keeps 4k candidates, at most 128, for the re-rank
+    assert b == pytest.approx(964 + 3840 + 400 + 128 * 3840)
 
 
 def test_serving_counter_record_and_traffic(tmp_path, monkeypatch):

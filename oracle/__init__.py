@@ -33,6 +33,10 @@ silent are listed in each function's docstring):
                                               -> :mod:`partition`
 * cosine dissimilarity 2 (1 - cos) as squared distance of normalized
   points                                      -> :mod:`cosine`
+* inner-product similarity (not a metric; Params(metric="ip")): the
+  dissimilarity -(x . y), the expansion test on exp(x . y)
+                                              -> :func:`distance.dissim`,
+                                                 :func:`exact.exact_graph_ip`
 * the number formats of the float path's scoring rows (bfloat16, FP8 E4M3
   with a row scale), from their definitions  -> :mod:`quantize`
 
@@ -47,10 +51,10 @@ quality of the search (which neighbours a given budget finds) has no printed
 value in the paper and is "parity unpinned" beyond those properties.
 """
 
-from .distance import sqdist, sqdist_many, INF_INT  # noqa: F401
+from .distance import dissim, dissim_many, inner_product, sqdist, sqdist_many, INF_INT  # noqa: F401
 from .restart import RestartOrder, restart_params, splitmix64_next  # noqa: F401
 from .exact import (ExactRows, GroupedExactRows, LazyExactGraph, exact_graph,  # noqa: F401
-                    exact_graph_loops, exact_row)
+                    exact_graph_ip, exact_graph_loops, exact_row)
 from .graph import OracleGraph, Params, budget  # noqa: F401
 from .ignns import ignns, SearchResult  # noqa: F401
 from .gnns import gnns  # noqa: F401

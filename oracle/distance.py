@@ -1,4 +1,6 @@
-"""Dissimilarity used throughout: squared Euclidean distance.
+"""Dissimilarities: squared Euclidean distance (the default), and the
+negated inner product (the inner-product similarity, a measure that is not
+a metric: Section 3 states the method for any similarity).
 
 The paper compares its synthetic Gaussian-mixture points with the Euclidean
 distance (Section 8.1.1); squaring preserves every ordering and keeps uint8
@@ -40,3 +42,24 @@ def sqdist_many(q: np.ndarray, X: np.ndarray) -> np.ndarray:
 def inf_of(dtype) -> object:
     """The 'absent' distance used to pad short neighbour lists."""
     return INF_INT if dtype == np.uint8 else float("inf")
+
+
+def inner_product(a: np.ndarray, b: np.ndarray) -> float:
+    """a . b in float64 from the inputs, accumulated left to right over the
+    coordinates."""
+    return float(np.cumsum(a.astype(np.float64) * b.astype(np.float64))[-1])
+
+
+def dissim(a: np.ndarray, b: np.ndarray, metric: str = "l2"):
+    """The dissimilarity the method ranks by (smaller = more similar):
+    squared L2, or for metric "ip" the negated inner product -(a . b)."""
+    if metric == "ip":
+        return -inner_product(a, b)
+    return sqdist(a, b)
+
+
+def dissim_many(q: np.ndarray, X: np.ndarray, metric: str = "l2") -> np.ndarray:
+    """dissim from one point to every row of X (same accumulation order)."""
+    if metric == "ip":
+        return -np.cumsum(X.astype(np.float64) * q.astype(np.float64)[None, :], axis=1)[:, -1]
+    return sqdist_many(q, X)

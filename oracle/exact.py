@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .distance import sqdist, sqdist_many
+from .distance import dissim_many, sqdist, sqdist_many
 from .graph import empty_lists
 
 _EXTRA = 8   # superset margin beyond k
@@ -275,3 +275,21 @@ class LazyExactGraph:
 
     def cached(self) -> int:
         return len(self._cache)
+
+
+def exact_graph_ip(X: np.ndarray, k: int):
+    """The exact k-nn graph by inner-product similarity: each node's k
+    others of largest inner product, i.e. the first k of (-(x_u . x_v), v),
+    v != u, sorted lexicographically (brute force, float64 dissimilarities
+    accumulated as in :func:`distance.dissim`)."""
+    n = X.shape[0]
+    kk = min(k, n - 1)
+    ids = np.full((n, k), -1, dtype=np.int64)
+    dist = np.full((n, k), np.inf, dtype=np.float64)
+    for u in range(n):
+        d = dissim_many(X[u], X, "ip")
+        d[u] = np.inf
+        o = np.lexsort((np.arange(n), d))[:kk]
+        ids[u, :kk] = o
+        dist[u, :kk] = d[o]
+    return ids, dist

@@ -26,6 +26,8 @@ class Params:
     depth     -- DEPTH of Algorithm 2; 0 is an exhaustive update used only
                  in tests (every snapshot node is considered).
     seed      -- seed of the restart permutations.
+    metric    -- "l2": squared Euclidean distance; "ip": inner-product
+                 similarity (float points), dissimilarity its negation.
     """
 
     k: int
@@ -34,6 +36,7 @@ class Params:
     e_den: int = 1
     depth: int = 2
     seed: int = 0x5EED
+    metric: str = "l2"
 
     def __post_init__(self):
         if self.k < 1:
@@ -44,6 +47,8 @@ class Params:
             raise ValueError("expansion e = e_num/e_den must be > 1")
         if self.depth < 0:
             raise ValueError("depth must be >= 0")
+        if self.metric not in ("l2", "ip"):
+            raise ValueError("metric must be 'l2' or 'ip'")
 
 
 def budget(n: int, k: int, speedup: int) -> int:

@@ -34,11 +34,12 @@ and optionally the ids in evaluation order (for parity checks).
 
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
 
-from .distance import sqdist
+from .distance import dissim
 from .graph import OracleGraph, Params, budget
 from .restart import RestartOrder
 
@@ -61,8 +62,13 @@ class SearchResult:
     sequence: list | None  # ids in evaluation order (if requested)
 
 
-def expansion_rejects(d_r, d_best, e_num: int, e_den: int) -> bool:
-    """True iff similarity(q, r) < s_max / e with s = 1/(1+d)."""
+def expansion_rejects(d_r, d_best, e_num: int, e_den: int, metric: str = "l2") -> bool:
+    """True iff similarity(q, r) < s_max / e.  Squared L2: s = 1/(1+d).
+    Inner product (unbounded, possibly negative): s = exp(q . r), so the
+    ratio test becomes s_max - s_r > ln e on the inner products, i.e.
+    d_r - d_best > ln(e_num / e_den) on the negated ones."""
+    if metric == "ip":
+        return d_r - d_best > math.log(e_num / e_den)
     return e_den * (1 + d_r) > e_num * (1 + d_best)
 
 
@@ -91,7 +97,7 @@ def ignns(g: OracleGraph, q, key: int, p: Params, n: int | None = None,
     state = {"evals": 0, "best": None}
 
     def evaluate(v: int):
-        d = sqdist(q, g.X[v])
+        d = dissim(q, g.X[v], p.metric)
         state["evals"] += 1
         visited.add(v)
         evaluated.append((d, v))
@@ -114,7 +120,7 @@ def ignns(g: OracleGraph, q, key: int, p: Params, n: int | None = None,
             if r is None:
                 return finish()
             d_r = evaluate(r)
-            if not expansion_rejects(d_r, state["best"], p.e_num, p.e_den):
+            if not expansion_rejects(d_r, state["best"], p.e_num, p.e_den, p.metric):
                 break
         # -- eager climb from r ---------------------------------------------
         c, d_c = r, d_r

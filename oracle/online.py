@@ -44,7 +44,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .distance import sqdist
+from .distance import dissim
 from .graph import OracleGraph, Params, empty_lists, write_list
 from .ignns import ignns
 
@@ -61,7 +61,8 @@ class BatchResult:
     sims: list                  # search evals + (b - 1) + update evals
 
 
-def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int):
+def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int,
+                      metric: str = "l2"):
     """Step (iii) for one batch point: returns (proposals, update evals)."""
     n = g.n
     props = []
@@ -73,7 +74,7 @@ def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int):
             if u in known:
                 d = known[u]
             else:
-                d = sqdist(y, g.X[u])
+                d = dissim(y, g.X[u], metric)
                 upd += 1
             props.append((u, d, src))
         return props, upd
@@ -87,7 +88,7 @@ def _update_proposals(g: OracleGraph, y, src: int, R_pairs: list, depth: int):
             if ell == 1:
                 d = known[u]
             else:
-                d = sqdist(y, g.X[u])
+                d = dissim(y, g.X[u], metric)
                 upd += 1
             props.append((u, d, src))
             if ell < depth:
@@ -101,7 +102,7 @@ def point_search_and_proposals(g, Y: np.ndarray, i: int, p: Params, record: bool
     n + i): (search result, proposals, update evaluations).  The batch's
     points are independent in these steps."""
     r = ignns(g, Y[i], key=g.n + i, p=p, record=record)
-    props, upd = _update_proposals(g, Y[i], g.n + i, r.pairs, p.depth)
+    props, upd = _update_proposals(g, Y[i], g.n + i, r.pairs, p.depth, p.metric)
     return r, props, upd
 
 
@@ -130,7 +131,7 @@ def search_and_propose(g, Y: np.ndarray, p: Params, record: bool = False, run_po
         cand = list(search[i].pairs)
         for j in range(b):
             if j != i:
-                cand.append((sqdist(Y[i], Y[j]), n + j))
+                cand.append((dissim(Y[i], Y[j], p.metric), n + j))
         cand.sort()
         final_lists.append(cand[:k])
     proposals = []
@@ -219,7 +220,7 @@ def insert_sequential_literal(g: OracleGraph, y, p: Params) -> OracleGraph:
     if p.depth == 0:
         targets = list(range(n))
         for node in targets:
-            _literal_add(out, node, sqdist(y, g.X[node]), n)
+            _literal_add(out, node, dissim(y, g.X[node], p.metric), n)
     else:
         Q = [v for _, v in res.pairs]
         for _ in range(p.depth):
@@ -230,7 +231,7 @@ def insert_sequential_literal(g: OracleGraph, y, p: Params) -> OracleGraph:
                     continue
                 processed.add(node)
                 Q_next.extend(out.neighbours(node))
-                d = sqdist(y, g.X[node])
+                d = dissim(y, g.X[node], p.metric)
                 _literal_add(out, node, d, n)
             Q = Q_next
     write_list(out.ids, out.dist, n, res.pairs)

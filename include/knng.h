@@ -78,8 +78,22 @@ typedef enum {
  * KNNG_METRIC_COSINE (float data only): points are normalized to unit length
  * when stored and when searched, and the dissimilarity is the squared
  * distance of the normalized points, 2 (1 - cos), in [0, 4]; a zero vector
- * stays zero.  The method applies to any dissimilarity (Section 3). */
-typedef enum { KNNG_METRIC_L2 = 0, KNNG_METRIC_COSINE = 1 } knng_metric;
+ * stays zero.  The method applies to any dissimilarity (Section 3).
+ * KNNG_METRIC_INNER_PRODUCT (float data with KNNG_SCORE_EXACT only): the
+ * dissimilarity is the negated inner product -(x . y), float32, possibly
+ * negative; a similarity that is not a metric.  The expansion test takes the
+ * similarity exp(x . y), so a candidate is dropped when its dissimilarity
+ * exceeds the best one's by more than ln(expansion_num / expansion_den).
+ * Every distance handed out or taken in (search results, knng_get_lists,
+ * knng_load) is that float value; lists are ordered by it ascending (the
+ * largest inner product first) and padded with +infinity.  Partitioning,
+ * partitioned search and the GNNS baseline take the squared L2 distance
+ * only and reject such a graph with KNNG_EINVAL. */
+typedef enum {
+  KNNG_METRIC_L2 = 0,
+  KNNG_METRIC_COSINE = 1,
+  KNNG_METRIC_INNER_PRODUCT = 2
+} knng_metric;
 
 /*
  * Parameters (Section 3 and Algorithm 2 of the paper).

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libknng.so")
 KNNG_OK, KNNG_EINVAL, KNNG_ECAPACITY, KNNG_ENOMEM, KNNG_EDEVICE, KNNG_ESTATE = 0, -1, -2, -3, -4, -5
 KNNG_U8, KNNG_F32 = 0, 1
 KNNG_SCORE_EXACT, KNNG_SCORE_BF16, KNNG_SCORE_FP8, KNNG_SCORE_BF16_MFMA = 0, 1, 2, 3
-KNNG_METRIC_L2, KNNG_METRIC_COSINE = 0, 1
+KNNG_METRIC_L2, KNNG_METRIC_COSINE, KNNG_METRIC_INNER_PRODUCT = 0, 1, 2
 
 STATUS_NAMES = {0: "KNNG_OK", -1: "KNNG_EINVAL", -2: "KNNG_ECAPACITY", -3: "KNNG_ENOMEM",
                 -4: "KNNG_EDEVICE", -5: "KNNG_ESTATE"}

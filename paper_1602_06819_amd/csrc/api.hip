@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -182,10 +183,15 @@ knng_status check_params(const knng_params* p) {
     return fail(KNNG_EINVAL, "unknown score %d", p->score);
   if (p->dtype == KNNG_U8 && p->score != KNNG_SCORE_EXACT)
     return fail(KNNG_EINVAL, "uint8 data requires KNNG_SCORE_EXACT");
-  if (p->metric != KNNG_METRIC_L2 && p->metric != KNNG_METRIC_COSINE)
+  if (p->metric != KNNG_METRIC_L2 && p->metric != KNNG_METRIC_COSINE &&
+      p->metric != KNNG_METRIC_INNER_PRODUCT)
     return fail(KNNG_EINVAL, "unknown metric %d", p->metric);
   if (p->metric == KNNG_METRIC_COSINE && p->dtype != KNNG_F32)
     return fail(KNNG_EINVAL, "the cosine metric needs float data");
+  if (p->metric == KNNG_METRIC_INNER_PRODUCT &&
+      (p->dtype != KNNG_F32 || p->score != KNNG_SCORE_EXACT))
+    return fail(KNNG_EINVAL, "the inner-product metric needs float data with "
+                             "KNNG_SCORE_EXACT");
   if (p->dtype == KNNG_U8 && p->dim > 256)
     return fail(KNNG_EINVAL, "uint8 data supports dim <= 256 (got %d)", p->dim);
   if (p->dtype == KNNG_F32) {
@@ -226,7 +232,8 @@ StorageLayout storage_layout(const knng_params& p) {
   S.format = row_format(p);
   S.is_float = p.dtype == KNNG_F32;
   S.cosine = p.metric == KNNG_METRIC_COSINE;
-  S.pad = S.is_float ? (int32_t)0x7f800000 : DIST_PAD_I32;
+  S.ip = p.metric == KNNG_METRIC_INNER_PRODUCT;
+  S.pad = S.ip ? (int32_t)SORT_INF : S.is_float ? (int32_t)0x7f800000 : DIST_PAD_I32;
   S.mstride = S.is_float ? (int)round_up(p.dim, 4) : 0;
   switch (S.format) {
     case ROW_I8: S.row_bytes = (int)round_up(p.dim, 16); break;
@@ -411,6 +418,8 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
     }
   }
   a.pad_bits = (uint32_t)S.pad;
+  a.ip = S.ip ? 1 : 0;
+  a.ip_margin = (float)std::log((double)g->p.expansion_num / (double)g->p.expansion_den);
   if (search_sets_global(g->n)) {
     a.gvis = at<uint32_t>(g->ws, W.off_sets);
     a.gvis_slots = W.set_slots;
@@ -428,8 +437,9 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
 // Row group of a read-only search: raw points, caller's outputs.
 SearchRows query_rows(const void* q, int64_t m, const uint64_t* keys, uint64_t key_base,
                       int32_t* ids, void* d, int stride, int32_t* evals, int32_t* list_reads,
-                      int32_t* trace, int64_t trace_stride) {
+                      int32_t* trace, int64_t trace_stride, bool decode = false) {
   SearchRows r{};
+  r.decode = decode ? 1 : 0;
   r.qraw = q;
   r.keys = keys;
   r.key_base = key_base;
@@ -527,6 +537,7 @@ knng_status exact_lists_range(knng_graph* g, int64_t q_first, int64_t nq, int64_
   a.row_bytes = rb;
   a.k = S.k;
   a.exclude_self = exclude_self ? 1 : 0;
+  a.ip = S.ip ? 1 : 0;
   if (S.is_float) {
     const int km = exact_km(S.k);
     uint64_t* cand = at<uint64_t>(g->ws, W.off_cand);
@@ -550,6 +561,7 @@ knng_status exact_lists_range(knng_graph* g, int64_t q_first, int64_t nq, int64_
       r.cand = cand;
       r.km = km;
       r.k = S.k;
+      r.ip = S.ip ? 1 : 0;
       r.out_ids = out_ids + q0 * out_stride;
       r.out_d = out_d + q0 * out_stride;
       r.out_stride = out_stride;
@@ -654,6 +666,7 @@ knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int
   pa.list_ids = ids + n * S.k_pad;
   pa.list_d = dist + n * S.k_pad;
   pa.pad = S.pad;
+  pa.ip = S.ip ? 1 : 0;
   {
     Timed t(g, KNNG_STAGE_PEERS, stream);
     KNNG_TRY(launch_peers(pa, stream), "peers launch");
@@ -684,6 +697,7 @@ knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int
   ua.sims = sims_dev;
   ua.stats = stats_dev;
   ua.n = (int32_t)n;
+  ua.ip = S.ip ? 1 : 0;
   ua.front_cap = (int)update_sizes(S.k, g->p.depth).front_cap;
   if (update_fronts_global(ua.front_cap)) ua.gfront = at<int32_t>(g->ws, W.off_fronts);
   if (update_sets_global(n, ua.front_cap)) {
@@ -813,7 +827,8 @@ knng_status check_partitioned(knng_graph* g, const void* q_dev, int64_t m,
   if (g->S.is_float && g->S.format != ROW_F32)
     return fail(KNNG_EINVAL, "partitioned search is built for uint8 graphs and float graphs "
                              "with float32 scoring");
-  if (g->S.cosine) return fail(KNNG_EINVAL, "partitioned search does not take the cosine metric");
+  if (g->S.cosine || g->S.ip)
+    return fail(KNNG_EINVAL, "partitioned search takes the squared L2 distance only");
   knng_status s;
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
@@ -979,7 +994,7 @@ knng_status knng_load(const knng_params* p, const void* x_dev, int64_t n, const 
     return cleanup(s);
   if ((s = dev(launch_copy_lists(ids_dev, (const int32_t*)d_dev, S.k,
                                  at<int32_t>(g->st, S.off_ids), at<int32_t>(g->st, S.off_dist),
-                                 S.k_pad, n, S.k, n, S.pad, stream),
+                                 S.k_pad, n, S.k, n, S.pad, stream, S.ip ? 1 : 0),
                "copy lists")) != KNNG_OK)
     return cleanup(s);
   g->n = n;
@@ -1003,7 +1018,7 @@ knng_status knng_search(knng_graph* g, const void* q_dev, int64_t m, const uint6
     return fail(KNNG_EINVAL, "trace_stride %lld is below the budget %lld",
                 (long long)trace_stride, (long long)budget(g->n, g->S.k, g->p.speedup));
   s = run_search(g, query_rows(q_dev, m, keys_dev, 0, ids_dev, d_dev, g->S.k, evals_dev,
-                                list_reads_dev, trace_dev, trace_stride),
+                                list_reads_dev, trace_dev, trace_stride, g->S.ip),
                  nullptr, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   return ok();
@@ -1021,6 +1036,7 @@ knng_status knng_search_gnns(knng_graph* g, const void* q_dev, int64_t m,
   if (g->S.is_float && g->S.format != ROW_F32)
     return fail(KNNG_EINVAL, "the GNNS baseline is built for uint8 graphs and float graphs "
                              "with float32 scoring");
+  if (g->S.ip) return fail(KNNG_EINVAL, "the GNNS baseline takes the squared L2 distance only");
   if ((s = check_ptr(q_dev, "q_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(keys_dev, "keys_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
@@ -1046,7 +1062,8 @@ knng_status knng_query(knng_graph* g, const void* q_dev, int64_t m, int32_t* ids
   if ((s = check_ptr(ids_dev, "ids_dev")) != KNNG_OK) return s;
   if ((s = check_ptr(d_dev, "d_dev")) != KNNG_OK) return s;
   s = run_search(g, query_rows(q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount,
-                                ids_dev, d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0),
+                                ids_dev, d_dev, g->S.k, evals_dev, list_reads_dev, nullptr, 0,
+                                g->S.ip),
                  nullptr, KNNG_STAGE_QUERY, stream);
   if (s != KNNG_OK) return s;
   g->qcount += m;
@@ -1133,7 +1150,7 @@ knng_status knng_epoch(knng_graph* g, const void* x_dev, int64_t b, const void* 
   // (keys 2^62 + query count), both on the snapshot of n nodes
   SearchRows qr = query_rows(q_dev, m, nullptr, (uint64_t)QUERY_KEY_BASE + (uint64_t)g->qcount,
                              q_ids_dev, q_d_dev, g->S.k, q_evals_dev, q_list_reads_dev,
-                             nullptr, 0);
+                             nullptr, 0, g->S.ip);
   SearchRows ir = insert_rows(g, x_dev, b);
   if ((s = run_search(g, ir, &qr, KNNG_STAGE_SEARCH, stream)) != KNNG_OK) return s;
   g->qcount += m;
@@ -1151,7 +1168,8 @@ knng_status knng_get_lists(const knng_graph* g, int64_t first, int64_t count, in
   const StorageLayout& S = g->S;
   KNNG_TRY(launch_copy_lists(at<int32_t>(g->st, S.off_ids) + first * S.k_pad,
                              at<int32_t>(g->st, S.off_dist) + first * S.k_pad, S.k_pad, ids_dev,
-                             (int32_t*)d_dev, S.k, count, S.k, g->n, S.pad, stream),
+                             (int32_t*)d_dev, S.k, count, S.k, g->n, S.pad, stream,
+                             S.ip ? 2 : 0),
            "copy lists");
   return ok();
 }
@@ -1209,6 +1227,8 @@ knng_status knng_partition(knng_graph* g, int32_t p, int32_t iters, int32_t imb_
   if (p < 1 || p > 64) return fail(KNNG_EINVAL, "p must be 1 .. 64");
   if (p > g->n) return fail(KNNG_EINVAL, "p exceeds the number of nodes");
   if (iters < 1) return fail(KNNG_EINVAL, "iters must be >= 1");
+  if (g->S.ip)
+    return fail(KNNG_EINVAL, "partitioning needs distances >= 0 (not the inner-product metric)");
   if (imb_den < 1 || imb_num < imb_den || imb_num > 64 * imb_den)
     return fail(KNNG_EINVAL, "imbalance num/den must be in [1, 64] with den >= 1");
   knng_status s;

@@ -13,6 +13,23 @@
 
 namespace knng {
 
+// Order-preserving 32-bit keys of float values of either sign (the
+// dissimilarity of the inner-product metric, -(x . y), may be negative):
+// non-negative floats get the sign bit set, negative ones are inverted, so
+// the keys compare as unsigned integers like the values.  +inf maps to
+// SORT_INF.  Non-negative distances (squared L2) keep their plain bits.
+constexpr uint32_t SORT_INF = 0xff800000u;
+__host__ __device__ __forceinline__ uint32_t sortable_from_float(float f) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
+  if ((b & 0x7fffffffu) == 0u) return 0x80000000u;        // -0 and +0: one key
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float float_from_sortable(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __builtin_bit_cast(float, b);
+}
+
+
 constexpr int WAVE = 64;
 constexpr uint64_t KEY_INF = ~0ull;
 constexpr int32_t DIST_PAD_I32 = 0x7fffffff;

@@ -175,14 +175,18 @@ __device__ __forceinline__ void canon_load_query(const float* q, int dim, float 
 // `base` (`stride` floats per row, 16-byte aligned, zero padded).  Returns
 // in lane c the distance bits of its candidate (+inf bits when none).  PB
 // passes of 4 candidates have their loads in flight together.  Must be
-// called by the whole wavefront in uniform control flow.
+// called by the whole wavefront in uniform control flow.  With `ip` the
+// same order of operations sums the products q x (one fused multiply-add
+// per coordinate) and the result is the sortable key of -(q . x) (SORT_INF
+// when none).
 template <int CPL, int PB>
 __device__ __forceinline__ uint32_t canon_dist_lanes(const float (&qc)[CPL][4], const float* base,
-                                                     int64_t stride, int chunks, int32_t cid) {
+                                                     int64_t stride, int chunks, int32_t cid,
+                                                     bool ip = false) {
   const int lane = lane_id();
   const int slot = lane / CANON_G;
   const int sub = lane % CANON_G;
-  uint32_t out = 0x7f800000u;
+  uint32_t out = ip ? SORT_INF : 0x7f800000u;
   const uint64_t any = ballot(cid >= 0);
   const int hi = any ? 64 - __clzll((long long)any) : 0;   // highest candidate lane + 1
   const int passes = (hi + 3) / 4;
@@ -206,16 +210,24 @@ __device__ __forceinline__ uint32_t canon_dist_lanes(const float (&qc)[CPL][4], 
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       float s = 0.f;
+      if (ip) {
 #pragma unroll
-      for (int t = 0; t < CPL; ++t)
+        for (int t = 0; t < CPL; ++t)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float d = qc[t][e] - xv[pb][t][e];
-          s = __builtin_fmaf(d, d, s);
-        }
+          for (int e = 0; e < 4; ++e) s = __builtin_fmaf(qc[t][e], xv[pb][t][e], s);
+      } else {
+#pragma unroll
+        for (int t = 0; t < CPL; ++t)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float d = qc[t][e] - xv[pb][t][e];
+            s = __builtin_fmaf(d, d, s);
+          }
+      }
       s = group_sum<CANON_G>(s);
       const float got = __int_as_float(shfl_i32(__float_as_int(s), (lane % 4) * CANON_G));
-      if (lane / 4 == p0 + pb && cid >= 0) out = __float_as_uint(got);
+      if (lane / 4 == p0 + pb && cid >= 0)
+        out = ip ? sortable_from_float(-got) : __float_as_uint(got);
     }
   }
   return out;

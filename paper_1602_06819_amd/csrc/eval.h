@@ -100,6 +100,7 @@ template <int G, int CPL>
 struct EvalI8 {
   v4i qc[CPL];
   int32_t qn;
+  bool ip = false;       // (float rows only)
   // query = row `i` of `rows`
   __device__ void load(const void* rows, int row_bytes, int dim, int64_t i) {
     qn = load_query_rows<G, CPL>((const int8_t*)rows + i * row_bytes, row_bytes, qc);
@@ -112,12 +113,13 @@ struct EvalI8 {
 template <int CCPL, int CPB>
 struct EvalF32 {
   float qc[CCPL][4];
+  bool ip = false;       // inner-product metric: keys of -(q . x)
   __device__ void load(const void* rows, int row_bytes, int dim, int64_t i) {
     canon_load_query<CCPL>((const float*)((const char*)rows + i * row_bytes), dim, qc);
   }
   __device__ uint32_t dist(const void* rows, int row_bytes, int32_t idx, bool load, int) {
     return canon_dist_lanes<CCPL, CPB>(qc, (const float*)rows, row_bytes / 4, row_bytes / 16,
-                                       load ? idx : -1);
+                                       load ? idx : -1, ip);
   }
 };
 

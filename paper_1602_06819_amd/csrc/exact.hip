@@ -9,6 +9,7 @@
 // integer distance.
 //
 // float32 points: the same expansion with q.x from v_mfma_f32_16x16x4_f32
+// (for the inner-product metric, -(q.x) itself as a sortable key)
 // selects KM >= k candidates per node (clamped at zero); k_rerank_f32 then
 // computes the stored float32 distance of each candidate and keeps the k
 // best by it.  The expansion's rounding error (a few units in the last
@@ -122,8 +123,12 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
               acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[dt][c][e], bq[t][c][e], acc, 0, 0, 0);
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
-            float v = __uint_as_float(qn[t]) + __uint_as_float(dn[dt][rr]) - 2.f * acc[rr];
-            dist[rr] = __float_as_uint(v > 0.f ? v : 0.f);
+            if (a.ip) {
+              dist[rr] = sortable_from_float(-acc[rr]);
+            } else {
+              float v = __uint_as_float(qn[t]) + __uint_as_float(dn[dt][rr]) - 2.f * acc[rr];
+              dist[rr] = __float_as_uint(v > 0.f ? v : 0.f);
+            }
           }
         } else {
           v4i acc = v4i{0, 0, 0, 0};
@@ -244,7 +249,8 @@ __global__ __launch_bounds__(256) void k_exact_f32_long(ExactArgs a) {
         const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
         const int32_t on = orow < a.nd ? orow : a.nd - 1;
         const float v = qn + __uint_as_float(a.dnorm[on]) - 2.f * acc[dt][rr];
-        const uint32_t dist = __float_as_uint(v > 0.f ? v : 0.f);
+        const uint32_t dist = a.ip ? sortable_from_float(-acc[dt][rr])
+                                   : __float_as_uint(v > 0.f ? v : 0.f);
         const bool ok = orow < a.nd &&
                         !(a.exclude_self && a.d_id_base + orow == a.q_id_base + q);
         const uint64_t key = ok ? make_key(dist, a.d_id_base + orow) : KEY_INF;
@@ -274,13 +280,15 @@ __global__ __launch_bounds__(64) void k_rerank_f32(RerankArgs a) {
   const uint64_t ck = lane < a.km ? a.cand[(int64_t)q * a.km + lane] : KEY_INF;
   const bool have = ck != KEY_INF;
   const int32_t cid = have ? key_id(ck) : -1;
-  const uint32_t d32 = canon_dist_lanes<CCPL, CPB>(qc, a.rows, a.stride, a.stride / 4, cid);
+  const uint32_t d32 =
+      canon_dist_lanes<CCPL, CPB>(qc, a.rows, a.stride, a.stride / 4, cid, a.ip != 0);
   uint64_t rk = KEY_INF;
   wave_topk_offer_ranked(rk, have, have ? make_key(d32, cid) : KEY_INF, a.k, tk_c, tk_r, tk_o);
   if (lane < a.out_stride) {
     const bool ok = lane < a.k && rk != KEY_INF;
+    const int32_t pad = a.ip ? (int32_t)SORT_INF : (int32_t)0x7f800000;
     a.out_ids[(int64_t)q * a.out_stride + lane] = ok ? key_id(rk) : -1;
-    a.out_d[(int64_t)q * a.out_stride + lane] = ok ? (int32_t)key_dist(rk) : (int32_t)0x7f800000;
+    a.out_d[(int64_t)q * a.out_stride + lane] = ok ? (int32_t)key_dist(rk) : pad;
   }
 }
 

@@ -33,6 +33,7 @@ struct StorageLayout {
   int norm_off = -1;     // byte offset of a float32 row term inside the row, or -1
   bool is_float = false;
   bool cosine = false; // rows normalized to unit length (cosine metric)
+  bool ip = false;     // inner-product metric: distances are sortable keys of -(x . y)
   int32_t pad = 0;     // distance padding pattern
   int64_t cap = 0;
   size_t off_vec = 0, off_scale = 0, off_qnorm = 0, off_master = 0, off_norms = 0, off_ids = 0,
@@ -102,6 +103,7 @@ struct ExactArgs {
   int32_t split_len;     // database rows per split (multiple of the tile)
   int32_t nsplit;
   int exclude_self;      // skip database id == query id
+  int ip;                // float32: candidates by the inner product (keys of -(q . x))
   int32_t* out_ids; int32_t* out_d; int out_stride;   // when nsplit == 1 and no cand
   uint64_t* partial;     // [nsplit][nq][k] keys when nsplit > 1
   uint64_t* cand;        // float32: [nq][km] candidate keys
@@ -112,6 +114,7 @@ struct RerankArgs {
   int32_t q_id_base; int32_t nq;            // nodes q_id_base .. + nq - 1
   const uint64_t* cand; int km;             // [nq][km] candidate keys
   int k;
+  int ip;                                   // inner-product dissimilarity keys
   int32_t* out_ids; int32_t* out_d; int out_stride;
 };
 
@@ -125,6 +128,7 @@ struct SearchRows {
   int32_t* out_list_reads;   // neighbour lists read per query (may be null)
   int32_t* trace; int64_t trace_stride;
   int32_t count;
+  int decode;            // write float32 dissimilarities, not sortable keys (inner product)
 };
 
 struct SearchArgs {
@@ -150,6 +154,8 @@ struct SearchArgs {
   SearchRows rows[2];
   int32_t m;             // rows[0].count + rows[1].count (set by the launcher)
   uint32_t pad_bits;     // distance padding of absent entries
+  int ip;                // inner-product metric: keys of -(q . x), additive expansion test
+  float ip_margin;       // ln(e_num / e_den): the inner-product expansion margin
   uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
   int32_t vis_words, vis_words_pad;    // set by the launcher from n
   int32_t restarts;      // GNNS mode: number of restarts (launch_search_gnns)
@@ -192,6 +198,7 @@ struct PeerArgs {
   const int32_t* res_ids; const int32_t* res_d;   // search results [b][k_pad]
   int32_t* list_ids; int32_t* list_d;             // lists of the new nodes [b][k_pad]
   int32_t pad;
+  int ip;                                         // inner-product dissimilarity keys
 };
 
 struct UpdateArgs {
@@ -211,6 +218,7 @@ struct UpdateArgs {
   int32_t set_words, set_words_pad;   // set by the launcher from n
   int front_cap;         // slots of one level array (largest expanded level)
   int32_t* gfront;       // level arrays in global memory [b][2][front_cap] (null: LDS)
+  int ip;                      // inner-product dissimilarity keys
 };
 
 struct MergeArgs {
@@ -266,7 +274,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit, int32_t pad, hipStream_t s);
+                             int k, int64_t id_limit, int32_t pad, hipStream_t s, int mode = 0);
 hipError_t launch_export_u8(const int8_t* vec, int row_bytes, int dim, int64_t rows,
                             uint8_t* out, hipStream_t s);
 hipError_t launch_export_f32(const float* rows, int stride, int dim, int64_t count, float* out,

@@ -157,9 +157,13 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) 
 // k .. dst_stride-1 of the destination are set to padding.  An id outside
 // [0, id_limit) becomes a padding entry, so lists supplied by a caller can
 // never make a kernel read outside the graph.
+// `mode` 1 turns float32 distances into sortable keys (lists supplied to the
+// library for the inner-product metric), 2 turns keys back into float32
+// distances (lists read out); 0 copies the bits.  `pad` is the stored
+// padding value (decoded like the entries in mode 2).
 __global__ void k_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit, int32_t pad) {
+                             int k, int64_t id_limit, int32_t pad, int mode) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = rows * dst_stride;
   if (i >= total) return;
@@ -169,21 +173,30 @@ __global__ void k_copy_lists(const int32_t* src_ids, const int32_t* src_d, int s
     int32_t id = src_ids ? src_ids[r * src_stride + j] : -1;
     bool ok = id >= 0 && (int64_t)id < id_limit;
     if (dst_ids) dst_ids[i] = ok ? id : -1;
-    if (dst_d) dst_d[i] = (ok && src_d) ? src_d[r * src_stride + j] : pad;
+    if (dst_d) {
+      int32_t v = pad;
+      if (ok && src_d) {
+        v = src_d[r * src_stride + j];
+        if (mode == 1) v = (int32_t)sortable_from_float(__int_as_float(v));
+      }
+      // mode 2 decodes stored keys, the padding included
+      if (mode == 2) v = __float_as_int(float_from_sortable((uint32_t)v));
+      dst_d[i] = v;
+    }
   } else {
     if (dst_ids) dst_ids[i] = -1;
-    if (dst_d) dst_d[i] = pad;
+    if (dst_d) dst_d[i] = mode == 2 ? __float_as_int(float_from_sortable((uint32_t)pad)) : pad;
   }
 }
 
 hipError_t launch_copy_lists(const int32_t* src_ids, const int32_t* src_d, int src_stride,
                              int32_t* dst_ids, int32_t* dst_d, int dst_stride, int64_t rows,
-                             int k, int64_t id_limit, int32_t pad, hipStream_t s) {
+                             int k, int64_t id_limit, int32_t pad, hipStream_t s, int mode) {
   int64_t total = rows * dst_stride;
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_lists, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      src_ids, src_d, src_stride, dst_ids, dst_d, dst_stride, rows, k, id_limit,
-                     pad);
+                     pad, mode);
   return hipGetLastError();
 }
 

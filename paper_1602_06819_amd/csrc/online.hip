@@ -26,6 +26,7 @@ __global__ __launch_bounds__(64) void k_peers(PeerArgs a) {
   if (i >= a.b) return;
   Eval ev;
   ev.load(a.bvec, a.row_bytes, a.dim, i);
+  ev.ip = a.ip != 0;
   uint64_t rk = KEY_INF;
   if (lane < a.k) {
     int32_t id = a.res_ids[(int64_t)i * a.k_pad + lane];
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
   }
   bool fresh1 = u >= 0 && bit_set(done_bits, u);
   int32_t thr1 = fresh1 ? a.nbr_d[(int64_t)u * a.k_pad + a.k - 1] : 0;
-  stage(fresh1 && du < thr1, u, du);
+  stage(fresh1 && (uint32_t)du < (uint32_t)thr1, u, du);
   uint64_t m1 = ballot(fresh1);
   if (fresh1) front[rank_below(m1)] = u;
   int fcount = __popcll(m1);
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
   if (a.depth >= 2) {
     Eval ev;
     ev.load(a.bvec, a.row_bytes, a.dim, i);
+    ev.ip = a.ip != 0;
     for (int level = 2; level <= a.depth; ++level) {
       const bool keep = level < a.depth;     // this level is expanded further
       if (lane == 0) next_count = 0;
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(64) void k_update(UpdateArgs a) {
         __syncthreads();
         int cnt = total - c0 < WAVE ? total - c0 : WAVE;
         int32_t d = (int32_t)ev.dist(a.vec, a.row_bytes, w, fresh, cnt);
-        stage(fresh && d < thr, w, d);
+        stage(fresh && (uint32_t)d < (uint32_t)thr, w, d);
         uint64_t mf = ballot(fresh);
         upd += __popcll(mf);
         if (keep) {

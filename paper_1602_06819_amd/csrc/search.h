@@ -186,16 +186,30 @@ struct ScoreFP8 {
   }
 };
 
+// float32 rows.  With the inner-product metric the score is the sortable
+// key of -(q . x), and the expansion test, on exp(q . x), discards a restart
+// whose inner product is more than ln e below the best one's.
 template <int G, int CPL>
 struct ScoreF32 {
   static constexpr bool kSide = false;
   static constexpr bool kSide2 = false, kMfma = false, kBatch = false, kWide = false;
   float q[CPL][4];
+  bool ip;
+  float margin;
   __device__ __forceinline__ void load(const SearchArgs& a, const SearchRows& r, int32_t qi) {
     load_query_f32<G, CPL, 4>(a, r, qi, q);
+    ip = a.ip != 0;
+    margin = a.ip_margin;
   }
   __device__ __forceinline__ uint32_t dist(const v4i (&x)[CPL], uint32_t) const {
     float s = 0.f;
+    if (ip) {
+#pragma unroll
+      for (int pp = 0; pp < CPL; ++pp)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s = fmaf(q[pp][e], __int_as_float(x[pp][e]), s);
+      return sortable_from_float(-group_sum<G>(s));
+    }
 #pragma unroll
     for (int pp = 0; pp < CPL; ++pp)
 #pragma unroll
@@ -205,7 +219,8 @@ struct ScoreF32 {
       }
     return __float_as_uint(group_sum<G>(s));
   }
-  __device__ __forceinline__ static bool keep(uint32_t d, uint32_t best, int num, int den) {
+  __device__ __forceinline__ bool keep(uint32_t d, uint32_t best, int num, int den) const {
+    if (ip) return !(float_from_sortable(d) - float_from_sortable(best) > margin);
     return keep_f32(d, best, num, den);
   }
 };
@@ -654,7 +669,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         // candidate is tested against the best before the window, or its
         // own distance if that is smaller.
         const uint32_t bt = d < best ? d : best;
-        S = GNNS ? V : ballot(valid && Score::keep(d, bt, a.e_num, a.e_den));
+        S = GNNS ? V : ballot(valid && sc.keep(d, bt, a.e_num, a.e_den));
         if (GNNS && S) ++restarts_used;
       } else if (GNNS) {
         // steepest: the closest unvisited neighbour, if closer than current
@@ -755,16 +770,16 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       canon_load_query<CCPL>((const float*)R.qraw + (int64_t)qq * a.dim, a.dim, qc);
       const bool have = lane < kk && rk != KEY_INF;
       const int32_t cid = have ? key_id(rk) : -1;
-      const uint32_t d32 =
-          canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride, a.master_chunks, cid);
+      const uint32_t d32 = canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride,
+                                                       a.master_chunks, cid, a.ip != 0);
       const uint64_t nk = have ? make_key(d32, cid) : KEY_INF;
       uint64_t nk2 = KEY_INF;
       bool have2 = false;
       if (K2 && kk > WAVE) {
         have2 = WAVE + lane < kk && rk2 != KEY_INF;
         const int32_t cid2 = have2 ? key_id(rk2) : -1;
-        const uint32_t e32 =
-            canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride, a.master_chunks, cid2);
+        const uint32_t e32 = canon_dist_lanes<CCPL, CPB>(qc, a.master, a.master_stride,
+                                                         a.master_chunks, cid2, a.ip != 0);
         nk2 = have2 ? make_key(e32, cid2) : KEY_INF;
       }
       rk = KEY_INF;
@@ -774,7 +789,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     if (lane < R.out_stride) {
       const bool have = lane < a.k && rk != KEY_INF;
       R.out_ids[(int64_t)qi * R.out_stride + lane] = have ? key_id(rk) : -1;
-      R.out_d[(int64_t)qi * R.out_stride + lane] = have ? key_dist(rk) : a.pad_bits;
+      uint32_t dbits = have ? key_dist(rk) : a.pad_bits;
+      if (R.decode) dbits = __float_as_uint(float_from_sortable(dbits));
+      R.out_d[(int64_t)qi * R.out_stride + lane] = dbits;
     }
     if (lane == 0) {
       if (R.out_evals) R.out_evals[qi] = evals;

@@ -17,7 +17,8 @@ from ._lib import check, knng_params
 _DTYPES = {"u8": _lib.KNNG_U8, "f32": _lib.KNNG_F32}
 _SCORES = {"exact": _lib.KNNG_SCORE_EXACT, "bf16": _lib.KNNG_SCORE_BF16,
            "fp8": _lib.KNNG_SCORE_FP8, "bf16m": _lib.KNNG_SCORE_BF16_MFMA}
-_METRICS = {"l2": _lib.KNNG_METRIC_L2, "cosine": _lib.KNNG_METRIC_COSINE}
+_METRICS = {"l2": _lib.KNNG_METRIC_L2, "cosine": _lib.KNNG_METRIC_COSINE,
+            "ip": _lib.KNNG_METRIC_INNER_PRODUCT}
 
 
 @dataclass(frozen=True)

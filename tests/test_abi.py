@@ -57,6 +57,9 @@ def _p(L, **kw):
                                  dict(k=64, depth=4),
                                  dict(capacity=1), dict(max_batch=0), dict(max_batch=2000),
                                  dict(score=1), dict(dim=300), dict(metric=2), dict(metric=1),
+                                 dict(metric=3), dict(dtype=1, score=1, metric=2),
+                                 dict(dtype=1, score=2, metric=2),
+                                 dict(dtype=1, score=3, dim=128, metric=2),
                                  dict(dtype=1, score=0, dim=300), dict(dtype=1, score=1, dim=600),
                                  dict(dtype=1, score=2, dim=1100)])
 def test_invalid_params_are_rejected(L, bad):
@@ -68,7 +71,8 @@ def test_invalid_params_are_rejected(L, bad):
 
 def test_valid_float_shapes_and_cosine_are_accepted(L):
     for kw in (dict(dtype=1, score=2, dim=960, k=50), dict(dtype=1, score=1, dim=512),
-               dict(dtype=1, score=0, dim=256, metric=1), dict(depth=5), dict(depth=7)):
+               dict(dtype=1, score=0, dim=256, metric=1), dict(dtype=1, score=0, dim=256, metric=2),
+               dict(depth=5), dict(depth=7)):
         p = _p(L, **kw)
         assert L.lib.knng_storage_bytes(ctypes.byref(p)) > 0, (kw, L.last_error())
         assert L.lib.knng_workspace_bytes(ctypes.byref(p)) > 0

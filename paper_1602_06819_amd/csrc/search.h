@@ -415,8 +415,8 @@ struct ScoreBF16M {
 // are never evaluated or counted, as if absent -- with that partition's
 // budget; the rows' results are merged afterwards (k_merge_partitions).
 template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB,
-          bool GNNS = false, bool PART = false, bool K2 = false>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+          bool GNNS = false, bool PART = false, bool K2 = false, int WPE = 1>
+__global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[K2 ? 2 * WAVE : WAVE], tk_o[K2 ? 2 * WAVE : WAVE];
   static_assert(G % PB == 0, "pass groups must divide the passes");
@@ -695,7 +695,9 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
       const uint32_t d_now = d;
 
       // the next step: decide its candidates and issue their gathers first
+      // (one window draw and one issue site, whichever way the step went)
       if (!stop) {
+        bool draw = false;
         if (S) {
           const int32_t cur = readlane_i32(cid_now, f);
           dcur = (uint32_t)readlane_i32((int32_t)d_now, f);
@@ -722,24 +724,20 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             }
           }
           ++list_reads;
-          issue();
         } else if (!climbing) {
           const uint32_t x63 = (uint32_t)readlane_i32((int32_t)xL, WAVE - 1);
           P += WAVE;
           xP = (lcg.a * x63 + lcg.c) & mmask;
-          if (P >= a.m_mod) {
-            done = true;
-          } else {
-            window();
-            issue();
-          }
+          if (P >= a.m_mod) done = true;
+          else draw = true;
         } else if (GNNS && restarts_used >= a.restarts) {
           done = true;             // local maximum after the last restart
         } else {
           climbing = false;        // local maximum: restart
-          window();
-          issue();
+          draw = true;
         }
+        if (draw) window();
+        if (!done) issue();
       }
 
       // bookkeeping of this step: visited, trace, result list, count
@@ -806,21 +804,26 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 // of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
 // `vis_lds` is the LDS of the visited set (0 when it is global).
 template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false,
-          bool PART = false, int KPADS = 7>
+          bool PART = false, int KPADS = 7, bool STAGE16 = true, int WPE = 1>
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
-  // KPADS: the list strides this instantiation serves (1: 16, 2: 32, 4: 64)
+  // KPADS: the list strides this instantiation serves (1: 16, 2: 32, 4: 64).
+  // STAGE16: lists of 16 ids are gathered with every candidate's row and
+  // staged in LDS (a climb move then reads its list without a round trip);
+  // otherwise a move loads the one list it needs.  WPE: wavefronts per SIMD
+  // the register allocation is bounded for.
   const bool gvis = a.gvis != nullptr;
   // lists of more than 16 ids with a re-ranked reduced-precision score keep
   // up to 2 * WAVE candidates (two per lane)
   constexpr bool W2 = Score::kWide && CCPL > 0;
-#define KNNG_SEARCH_GO(LR, GV, K2)                                                       \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART, K2>),   \
+  constexpr int L16 = STAGE16 ? 16 : 0;
+#define KNNG_SEARCH_GO(LR, GV, K2)                                                            \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART, K2, WPE>),   \
                      dim3(grid), dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.keep > 2 * WAVE || (a.keep > WAVE && !(W2 && a.k_pad > 16)))
     return hipErrorInvalidValue;
   if (a.k_pad == 16) {
     if constexpr ((KPADS & 1) != 0) {
-      if (gvis) KNNG_SEARCH_GO(16, true, false); else KNNG_SEARCH_GO(16, false, false);
+      if (gvis) KNNG_SEARCH_GO(L16, true, false); else KNNG_SEARCH_GO(L16, false, false);
     } else {
       return hipErrorInvalidValue;
     }

@@ -503,6 +503,17 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
     bool climbing = false;
     const int64_t trace_base = (int64_t)qi * R.trace_stride;
 
+    // Restart windows resumed after a climb.  A window that accepts the
+    // restart of lane f has scored its positions after f too; the climb
+    // leaves the permutation where it was, so the next window starts at
+    // exactly those positions.  Their scores are kept (lane j of the next
+    // window = lane f + 1 + j of this one) and only the positions beyond are
+    // gathered; the visited probe and every decision are taken again.
+    constexpr bool REUSE = !PART;
+    uint32_t sd = 0xffffffffu;      // kept scores, lane view of the next window
+    int nsave = 0;                  // (uniform) positions kept at the last acceptance
+    int skip = 0;                   // (uniform) leading positions of this window kept
+
     int32_t cidL = -1;              // lane view
     uint32_t xL = 0;
     int32_t cidG[G];                // group view
@@ -532,21 +543,23 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
       for (int q = 0; q < PB; ++q) {
         const int p = gi * PB + q;
         const bool ok = cidG[p] >= 0;
-        const char* row = rows + (int64_t)(ok ? cidG[p] : 0) * a.row_bytes;
+        // rows of kept positions are not gathered again (their lists are)
+        const bool okr = ok && (!REUSE || p * SLOTS + slot >= skip);
+        const char* row = rows + (int64_t)(okr ? cidG[p] : 0) * a.row_bytes;
 #pragma unroll
         for (int pp = 0; pp < CPL; ++pp) {
           const int off = 16 * (sub + G * pp);
-          if (ok && off < a.coord_bytes)
+          if (okr && off < a.coord_bytes)
             xv[buf][q][pp] = *reinterpret_cast<const v4i*>(row + off);
           else
             xv[buf][q][pp] = v4i{0, 0, 0, 0};
         }
-        if (Score::kSide) sv[buf][q] = ok ? a.side[cidG[p]] : 0u;
+        if (Score::kSide) sv[buf][q] = okr ? a.side[cidG[p]] : 0u;
         if (Score::kSide2) {
           if (a.side2_off >= 0)
-            sv2[buf][q] = ok ? *reinterpret_cast<const uint32_t*>(row + a.side2_off) : 0u;
+            sv2[buf][q] = okr ? *reinterpret_cast<const uint32_t*>(row + a.side2_off) : 0u;
           else
-            sv2[buf][q] = ok ? a.side2[cidG[p]] : 0u;
+            sv2[buf][q] = okr ? a.side2[cidG[p]] : 0u;
         }
         if (PART) pg[p] = ok ? a.node_part[cidG[p]] : -1;
         if (LISTS) {
@@ -657,6 +670,7 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
 #pragma unroll
         for (int p = 0; p < G; ++p) to_lane(p);
       }
+      if (REUSE && skip > 0 && lane < skip) d = sd;   // kept scores of a resumed window
       const bool inpart = !PART || (spaced ? pg[0] : partL) == part;
       const bool valid = owner && cand >= 0 && !seen && inpart;
 
@@ -705,6 +719,10 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
             P += (uint32_t)f + 1u;
             xP = (lcg.a * (uint32_t)cur + lcg.c) & mmask;
             climbing = true;
+            if (REUSE) {
+              nsave = WAVE - 1 - f;
+              sd = (uint32_t)shfl_i32((int32_t)d_now, lane + f + 1 < WAVE ? lane + f + 1 : lane);
+            }
           }
           if (LISTS) {
             const int fc = spaced ? (CM ? f : f / G) : f;   // candidate index of lane f
@@ -730,13 +748,19 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
           xP = (lcg.a * x63 + lcg.c) & mmask;
           if (P >= a.m_mod) done = true;
           else draw = true;
+          nsave = 0;
         } else if (GNNS && restarts_used >= a.restarts) {
           done = true;             // local maximum after the last restart
         } else {
           climbing = false;        // local maximum: restart
           draw = true;
         }
-        if (draw) window();
+        // a window drawn after a climb resumes the kept positions
+        skip = draw ? nsave : 0;
+        if (draw) {
+          nsave = 0;
+          window();
+        }
         if (!done) issue();
       }
 

@@ -615,6 +615,10 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
       };
       auto pass = [&](int p, int buf, int q) __attribute__((always_inline)) {
         stage(p, buf, q);
+        if (REUSE && (p + 1) * SLOTS <= skip) {   // every score of the pass is kept
+          dg[p] = 0xffffffffu;
+          return;
+        }
         uint32_t dd;
         if constexpr (Score::kSide2)
           dd = sc.dist(xv[buf][q], sv[buf][q], sv2[buf][q]);

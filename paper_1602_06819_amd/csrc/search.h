@@ -415,7 +415,7 @@ struct ScoreBF16M {
 // are never evaluated or counted, as if absent -- with that partition's
 // budget; the rows' results are merged afterwards (k_merge_partitions).
 template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, int PB,
-          bool GNNS = false, bool PART = false, bool K2 = false, int WPE = 1>
+          bool GNNS = false, bool PART = false, bool K2 = false, int WPE = 1, bool KEEP = false>
 __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[K2 ? 2 * WAVE : WAVE], tk_o[K2 ? 2 * WAVE : WAVE];
@@ -503,13 +503,16 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
     bool climbing = false;
     const int64_t trace_base = (int64_t)qi * R.trace_stride;
 
-    // Restart windows resumed after a climb.  A window that accepts the
-    // restart of lane f has scored its positions after f too; the climb
+    // KEEP: restart windows resumed after a climb.  A window that accepts
+    // the restart of lane f has scored its positions after f too; the climb
     // leaves the permutation where it was, so the next window starts at
     // exactly those positions.  Their scores are kept (lane j of the next
     // window = lane f + 1 + j of this one) and only the positions beyond are
-    // gathered; the visited probe and every decision are taken again.
-    constexpr bool REUSE = !PART;
+    // gathered; the visited probe and every decision are taken again.  It
+    // pays where many wavefronts share the memory system (thousands of
+    // searches per launch) and costs a lone wavefront its extra
+    // instructions.
+    constexpr bool REUSE = KEEP && !PART;
     uint32_t sd = 0xffffffffu;      // kept scores, lane view of the next window
     int nsave = 0;                  // (uniform) positions kept at the last acceptance
     int skip = 0;                   // (uniform) leading positions of this window kept
@@ -832,20 +835,21 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
 // of 16, 32 or 64 ids are staged in LDS), GVIS from the caller's choice.
 // `vis_lds` is the LDS of the visited set (0 when it is global).
 template <class Score, int G, int CPL, int CCPL, int CPB, int PB = G, bool GNNS = false,
-          bool PART = false, int KPADS = 7, bool STAGE16 = true, int WPE = 1>
+          bool PART = false, int KPADS = 7, bool STAGE16 = true, int WPE = 1, bool KEEP = false>
 hipError_t launch_search_t(const SearchArgs& a, hipStream_t s, unsigned grid, size_t vis_lds) {
   // KPADS: the list strides this instantiation serves (1: 16, 2: 32, 4: 64).
   // STAGE16: lists of 16 ids are gathered with every candidate's row and
   // staged in LDS (a climb move then reads its list without a round trip);
   // otherwise a move loads the one list it needs.  WPE: wavefronts per SIMD
-  // the register allocation is bounded for.
+  // the register allocation is bounded for.  KEEP: kept restart-window
+  // scores (k_search).
   const bool gvis = a.gvis != nullptr;
   // lists of more than 16 ids with a re-ranked reduced-precision score keep
   // up to 2 * WAVE candidates (two per lane)
   constexpr bool W2 = Score::kWide && CCPL > 0;
   constexpr int L16 = STAGE16 ? 16 : 0;
-#define KNNG_SEARCH_GO(LR, GV, K2)                                                            \
-  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART, K2, WPE>),   \
+#define KNNG_SEARCH_GO(LR, GV, K2)                                                        \
+  hipLaunchKernelGGL((k_search<Score, G, CPL, LR, GV, CCPL, CPB, PB, GNNS, PART, K2, WPE, KEEP>), \
                      dim3(grid), dim3(64), vis_lds + (size_t)WAVE * (LR) * 4, s, a)
   if (a.keep > 2 * WAVE || (a.keep > WAVE && !(W2 && a.k_pad > 16)))
     return hipErrorInvalidValue;

@@ -312,3 +312,24 @@ def test_long_rows_search_and_insert(G, score, dim, k):
     gi, gd = (t.cpu().numpy() for t in g.lists())
     check_lists(Xall, gi, gd, self_ids=np.arange(len(Xall)))
     check_error(Xall, Xall, gi, gd)
+
+
+def test_large_launch_equals_small_launches(G):
+    """Launches of 2,048 searches or more keep the scored positions of a
+    restart window across the climb it starts (rows of up to 96 coordinates,
+    lists of up to 16 ids); smaller launches rescore them.  Both must give
+    the same results, evaluation order included."""
+    import torch
+    n, dim, k, m = 6000, 96, 10, 2304
+    X = f32_points(81, n + m, dim)
+    base, Q = X[:n], X[n:]
+    cfg = cfg_for(G, dim, k, n, m, speedup=6, e=(3, 2))
+    say(f"large vs small search launches n={n} m={m}")
+    g = G.KnnGraph.build_exact(cfg, torch.from_numpy(base).cuda())
+    keys = torch.arange(77, 77 + m, dtype=torch.int64)
+    Qd = torch.from_numpy(Q).cuda()
+    big = [t.cpu().numpy() for t in g.search(Qd, keys, trace=True)]
+    parts = [[t.cpu().numpy() for t in g.search(Qd[i:i + 1000], keys[i:i + 1000], trace=True)]
+             for i in range(0, m, 1000)]
+    for j in range(4):
+        assert np.array_equal(big[j], np.concatenate([p[j] for p in parts])), j

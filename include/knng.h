@@ -51,7 +51,8 @@ typedef enum {
                            exceeds params.max_batch                         */
   KNNG_ENOMEM = -3,     /* storage or workspace smaller than required      */
   KNNG_EDEVICE = -4,    /* a HIP call failed                               */
-  KNNG_ESTATE = -5      /* call not valid in the handle's state            */
+  KNNG_ESTATE = -5,     /* call not valid in the handle's state            */
+  KNNG_EUNSUPPORTED = -6 /* not available in this build of the library    */
 } knng_status;
 
 typedef enum { KNNG_U8 = 0, KNNG_F32 = 1 } knng_dtype;
@@ -398,6 +399,34 @@ knng_status knng_get_rows(const knng_graph* g, int64_t first, int64_t count, voi
  * launches (launches_host[KNNG_NUM_STAGES]); either pointer may be NULL. */
 knng_status knng_timing_enable(knng_graph* g, int enable);
 knng_status knng_timing_read(knng_graph* g, double* ms_host, int64_t* launches_host);
+
+/* Step counters of the iGNNS search kernel (Section 3), for profiling.
+ * Only the profiling build of the library (compiled with
+ * KNNG_STEP_COUNTERS: libknng_counters.so) counts; there every search
+ * launch adds its searches' totals, and knng_step_counters waits for the
+ * device, copies the KNNG_NUM_STEP_COUNTERS totals to counters_host (host
+ * memory, uint64_t) and clears them if reset is nonzero.  The regular
+ * build returns KNNG_EUNSUPPORTED.  A step is one gather-and-decide round
+ * of a search: a restart window (up to 64 permutation positions) or a list
+ * scan (the current node's list). */
+typedef enum {
+  KNNG_SC_SEARCHES = 0,         /* searches run                               */
+  KNNG_SC_EVALUATIONS = 1,      /* similarity evaluations committed           */
+  KNNG_SC_WINDOW_STEPS = 2,     /* restart-window steps                       */
+  KNNG_SC_SCAN_STEPS = 3,       /* list-scan steps                            */
+  KNNG_SC_WINDOW_CANDS = 4,     /* candidates of restart windows              */
+  KNNG_SC_SCAN_CANDS = 5,       /* candidates of list scans                   */
+  KNNG_SC_WINDOW_VISITED = 6,   /* window candidates found visited            */
+  KNNG_SC_SCAN_VISITED = 7,     /* list candidates found visited              */
+  KNNG_SC_WINDOW_COMMITTED = 8, /* evaluations committed by windows           */
+  KNNG_SC_SCAN_COMMITTED = 9,   /* evaluations committed by list scans        */
+  KNNG_SC_RESTARTS_TAKEN = 10,  /* restarts that started a climb              */
+  KNNG_SC_MOVES = 11,           /* climb moves                                */
+  KNNG_SC_WINDOW_KEPT = 12,     /* window candidates whose score was kept from
+                                   the window before (not gathered again)     */
+  KNNG_NUM_STEP_COUNTERS = 13
+} knng_step_counter;
+knng_status knng_step_counters(knng_graph* g, uint64_t* counters_host, int reset);
 
 /* Number of nodes (counting every insert already enqueued). */
 int64_t knng_size(const knng_graph* g);

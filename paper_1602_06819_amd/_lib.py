@@ -11,15 +11,22 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libknng.so")
+# KNNG_LIB selects another build of the same ABI (the profiling build,
+# libknng_counters.so, counts the search's steps)
+LIB_PATH = os.environ.get("KNNG_LIB") or os.path.join(HERE, "libknng.so")
 
 KNNG_OK, KNNG_EINVAL, KNNG_ECAPACITY, KNNG_ENOMEM, KNNG_EDEVICE, KNNG_ESTATE = 0, -1, -2, -3, -4, -5
+KNNG_EUNSUPPORTED = -6
+KNNG_NUM_STEP_COUNTERS = 13
+STEP_COUNTERS = ["searches", "evaluations", "window_steps", "scan_steps", "window_cands",
+                 "scan_cands", "window_visited", "scan_visited", "window_committed",
+                 "scan_committed", "restarts_taken", "moves", "window_kept"]
 KNNG_U8, KNNG_F32 = 0, 1
 KNNG_SCORE_EXACT, KNNG_SCORE_BF16, KNNG_SCORE_FP8, KNNG_SCORE_BF16_MFMA = 0, 1, 2, 3
 KNNG_METRIC_L2, KNNG_METRIC_COSINE, KNNG_METRIC_INNER_PRODUCT = 0, 1, 2
 
 STATUS_NAMES = {0: "KNNG_OK", -1: "KNNG_EINVAL", -2: "KNNG_ECAPACITY", -3: "KNNG_ENOMEM",
-                -4: "KNNG_EDEVICE", -5: "KNNG_ESTATE"}
+                -4: "KNNG_EDEVICE", -5: "KNNG_ESTATE", -6: "KNNG_EUNSUPPORTED"}
 
 EXPORTED = [
     "knng_storage_bytes", "knng_workspace_bytes", "knng_build_exact", "knng_load",
@@ -28,7 +35,7 @@ EXPORTED = [
     "knng_timing_enable", "knng_timing_read", "knng_row_bytes", "knng_get_rows",
     "knng_epoch", "knng_search_gnns", "knng_partition_scratch_bytes", "knng_partition",
     "knng_search_partitioned_scratch_bytes", "knng_search_partitioned",
-    "knng_search_partitioned_noalloc", "knng_insert_exact",
+    "knng_search_partitioned_noalloc", "knng_insert_exact", "knng_step_counters",
 ]
 
 STAGES = ["ingest", "exact", "search", "peers", "update", "merge", "query"]
@@ -124,6 +131,8 @@ def _load() -> ctypes.CDLL:
     lib.knng_search_partitioned_noalloc.argtypes = [vp, vp, i64, vp, vp, ctypes.c_int32, vp, vp,
                                                     vp, vp]
     lib.knng_search_partitioned_noalloc.restype = ctypes.c_int
+    lib.knng_step_counters.argtypes = [vp, P(ctypes.c_uint64), ctypes.c_int]
+    lib.knng_step_counters.restype = ctypes.c_int
     return lib
 
 

@@ -18,6 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libknng.so")
+# the profiling build: the same sources with the search's step counters
+COUNTERS_BUILD_DIR = os.path.join(HERE, "_build_counters")
+COUNTERS_LIB_PATH = os.path.join(HERE, "libknng_counters.so")
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -57,18 +60,24 @@ def _newest_header() -> float:
     return max(os.path.getmtime(h) for h in heads)
 
 
-def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False,
+          counters: bool = False) -> str:
     """Compile every HIP source and link the shared library; returns its path.
     With ``incremental``, objects newer than their source and every header
-    are kept."""
+    are kept.  ``counters`` builds the profiling variant (libknng_counters.so,
+    search step counters compiled in) instead."""
     hipcc = _hipcc()
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    bdir = COUNTERS_BUILD_DIR if counters else BUILD_DIR
+    out = COUNTERS_LIB_PATH if counters else LIB_PATH
+    os.makedirs(bdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    if counters:
+        inc.append("-DKNNG_STEP_COUNTERS=1")
     objs = []
     cmds = []
     newest_h = _newest_header()
     for src in sources():
-        obj = os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o")
+        obj = os.path.join(bdir, os.path.basename(src)[:-4] + ".o")
         objs.append(obj)
         if incremental and os.path.exists(obj):
             t = os.path.getmtime(obj)
@@ -89,11 +98,12 @@ def build(verbose: bool = False, jobs: int | None = None, incremental: bool = Fa
     jobs = max(jobs, 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(run, cmds))
-    tmp = LIB_PATH + ".tmp"
+    tmp = out + ".tmp"
     run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv,
+                counters="--counters" in sys.argv))

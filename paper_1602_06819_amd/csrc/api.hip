@@ -58,6 +58,10 @@ struct knng_graph {
   int64_t n;
   int64_t qcount;
   StageTimer timer;
+  unsigned long long* counters = nullptr;   // profiling build: step counters (device)
+  ~knng_graph() {
+    if (counters) (void)hipFree(counters);
+  }
 };
 
 namespace {
@@ -420,6 +424,13 @@ knng_status run_search(knng_graph* g, const SearchRows& r0, const SearchRows* r1
   a.pad_bits = (uint32_t)S.pad;
   a.ip = S.ip ? 1 : 0;
   a.ip_margin = (float)std::log((double)g->p.expansion_num / (double)g->p.expansion_den);
+#ifdef KNNG_STEP_COUNTERS
+  if (!g->counters) {
+    KNNG_TRY(hipMalloc((void**)&g->counters, KNNG_NUM_STEP_COUNTERS * 8), "counter buffer");
+    KNNG_TRY(hipMemset(g->counters, 0, KNNG_NUM_STEP_COUNTERS * 8), "counter buffer");
+  }
+  a.step_counters = g->counters;
+#endif
   if (search_sets_global(g->n)) {
     a.gvis = at<uint32_t>(g->ws, W.off_sets);
     a.gvis_slots = W.set_slots;
@@ -1367,6 +1378,26 @@ int64_t knng_budget(const knng_graph* g, int64_t n) {
 int64_t knng_query_count(const knng_graph* g) { return g ? g->qcount : -1; }
 
 const char* knng_last_error(void) { return g_err.c_str(); }
+
+knng_status knng_step_counters(knng_graph* g, uint64_t* counters_host, int reset) {
+  if (!g) return fail(KNNG_EINVAL, "graph is NULL");
+#ifdef KNNG_STEP_COUNTERS
+  if (!counters_host) return fail(KNNG_EINVAL, "counters_host is NULL");
+  KNNG_TRY(hipDeviceSynchronize(), "synchronize");
+  if (!g->counters) {
+    for (int i = 0; i < KNNG_NUM_STEP_COUNTERS; ++i) counters_host[i] = 0;
+    return ok();
+  }
+  KNNG_TRY(hipMemcpy(counters_host, g->counters, KNNG_NUM_STEP_COUNTERS * 8,
+                     hipMemcpyDeviceToHost), "copy counters");
+  if (reset) KNNG_TRY(hipMemset(g->counters, 0, KNNG_NUM_STEP_COUNTERS * 8), "clear counters");
+  return ok();
+#else
+  (void)counters_host;
+  (void)reset;
+  return fail(KNNG_EUNSUPPORTED, "step counters need the profiling build (KNNG_STEP_COUNTERS)");
+#endif
+}
 
 void knng_destroy(knng_graph* g) { delete g; }
 

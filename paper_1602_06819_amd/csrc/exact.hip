@@ -368,6 +368,8 @@ static hipError_t launch_exact_f32_km(const ExactArgs& a, hipStream_t s) {
   if (nch <= 1) return launch_exact_t<true, QT, 4, KM, 1>(a, s);
   if (nch <= 2) return launch_exact_t<true, QT, 4, KM, 2>(a, s);
   if (nch <= 4) return launch_exact_t<true, QT, 2, KM, 4>(a, s);
+  // 96 coordinates: 6 slices, not 8 with two of zeros
+  if (nch <= 6) return launch_exact_t<true, 1, 2, KM, 6>(a, s);
   if (nch <= 8) return launch_exact_t<true, 1, 2, KM, 8>(a, s);
   if (nch <= 16) return launch_exact_t<true, 1, 1, KM, 16>(a, s);
   dim3 grid((unsigned)((a.nq + 63) / 64));

@@ -159,6 +159,7 @@ struct SearchArgs {
   uint32_t* gvis; int64_t gvis_slots;  // global visited sets (null: LDS)
   int32_t vis_words, vis_words_pad;    // set by the launcher from n
   int32_t restarts;      // GNNS mode: number of restarts (launch_search_gnns)
+  unsigned long long* step_counters;   // profiling build: KNNG_NUM_STEP_COUNTERS totals
   // partitioned search (launch_search_part): node -> partition, partitions,
   // and the budget of each partition
   const int32_t* node_part; int32_t nparts; const int32_t* part_budget;

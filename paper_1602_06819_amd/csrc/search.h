@@ -589,6 +589,9 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
 
     int restarts_used = 0;          // GNNS: restarts taken
     bool done = Bq <= 0 || (GNNS && a.restarts <= 0);
+#ifdef KNNG_STEP_COUNTERS
+    unsigned long long stc[KNNG_NUM_STEP_COUNTERS] = {};   // this search's step counters
+#endif
     if (!done) {
       window();
       issue();
@@ -714,6 +717,18 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
       const bool mine = (C >> lane) & 1ull;
       const int32_t cid_now = cand;
       const uint32_t d_now = d;
+#ifdef KNNG_STEP_COUNTERS
+      {
+        const int w = climbing ? 1 : 0;                 // this step's kind
+        stc[KNNG_SC_WINDOW_STEPS + w] += 1;
+        stc[KNNG_SC_WINDOW_CANDS + w] += __popcll(ballot(owner && cand >= 0));
+        stc[KNNG_SC_WINDOW_VISITED + w] += __popcll(ballot(owner && cand >= 0 && seen));
+        stc[KNNG_SC_WINDOW_COMMITTED + w] += __popcll(C);
+        if (S && !stop) stc[climbing ? KNNG_SC_MOVES : KNNG_SC_RESTARTS_TAKEN] += 1;
+        if (REUSE && !climbing)
+          stc[KNNG_SC_WINDOW_KEPT] += __popcll(ballot(cand >= 0 && lane < skip));
+      }
+#endif
 
       // the next step: decide its candidates and issue their gathers first
       // (one window draw and one issue site, whichever way the step went)
@@ -822,6 +837,13 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
       if (R.decode) dbits = __float_as_uint(float_from_sortable(dbits));
       R.out_d[(int64_t)qi * R.out_stride + lane] = dbits;
     }
+#ifdef KNNG_STEP_COUNTERS
+    if (a.step_counters && lane == 0) {
+      stc[KNNG_SC_SEARCHES] = 1;
+      stc[KNNG_SC_EVALUATIONS] = (unsigned long long)evals;
+      for (int i = 0; i < KNNG_NUM_STEP_COUNTERS; ++i) atomicAdd(&a.step_counters[i], stc[i]);
+    }
+#endif
     if (lane == 0) {
       if (R.out_evals) R.out_evals[qi] = evals;
       if (R.out_list_reads) R.out_list_reads[qi] = list_reads;

@@ -296,6 +296,13 @@ class KnnGraph:
             return ids, d, ev, lr
         return ids, d, ev
 
+    def step_counters(self, reset: bool = False) -> dict:
+        """Search step counters since the last reset (the profiling build,
+        libknng_counters.so, only; the regular build raises KNNG_EUNSUPPORTED)."""
+        buf = (ctypes.c_uint64 * _lib.KNNG_NUM_STEP_COUNTERS)()
+        check(_lib.lib.knng_step_counters(self._h, buf, 1 if reset else 0))
+        return dict(zip(_lib.STEP_COUNTERS, (int(v) for v in buf)))
+
     def timing(self, enable: bool) -> None:
         """Start (clearing earlier totals) or stop per-stage event timing."""
         check(_lib.lib.knng_timing_enable(self._h, 1 if enable else 0))

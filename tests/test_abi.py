@@ -101,3 +101,9 @@ def test_null_arguments_are_rejected_before_any_launch(L):
     st = L.lib.knng_insert_batch(None, None, 1, None, None, None, None)
     assert st == L.KNNG_EINVAL
     assert L.lib.knng_size(None) == -1
+
+
+def test_step_counters_reject_null_handle(L):
+    buf = (ctypes.c_uint64 * L.KNNG_NUM_STEP_COUNTERS)()
+    assert L.lib.knng_step_counters(None, buf, 0) == L.KNNG_EINVAL
+    assert len(L.STEP_COUNTERS) == L.KNNG_NUM_STEP_COUNTERS

@@ -124,6 +124,9 @@ class Timed {
 
 constexpr size_t ALIGN = 256;
 constexpr int64_t PARTIAL_LISTS = 32768;
+// batches from this size on score their peers with the exact graph's tiles
+// (one wavefront per point is cheaper below: a few short launches fewer)
+constexpr int64_t PEER_TILE_MIN = 1024;
 constexpr int64_t QUERY_KEY_BASE = (int64_t)1 << 62;
 
 size_t take(size_t& cur, size_t bytes) {
@@ -528,11 +531,12 @@ knng_status ingest(knng_graph* g, const void* x, int64_t m, int64_t first, hipSt
 // out_d with row stride out_stride.
 knng_status exact_lists_range(knng_graph* g, int64_t q_first, int64_t nq, int64_t d_first,
                               int64_t nd, bool exclude_self, int32_t* out_ids, int32_t* out_d,
-                              int out_stride, hipStream_t stream, bool split_ok = true) {
+                              int out_stride, hipStream_t stream, bool split_ok = true,
+                              int stage = KNNG_STAGE_EXACT) {
   const StorageLayout& S = g->S;
   const WorkspaceLayout& W = g->W;
   if (nq <= 0 || nd <= 0) return KNNG_OK;
-  Timed t(g, KNNG_STAGE_EXACT, stream);
+  Timed t(g, stage, stream);
   const int rb = S.is_float ? S.mstride * 4 : S.row_bytes;
   const char* rows = S.is_float ? at<char>(g->st, S.off_master) : at<char>(g->st, S.off_vec);
   const uint32_t* norms = at<uint32_t>(g->st, S.off_norms);
@@ -678,7 +682,18 @@ knng_status insert_after_search(knng_graph* g, int64_t b, int32_t* sims_dev, int
   pa.list_d = dist + n * S.k_pad;
   pa.pad = S.pad;
   pa.ip = S.ip ? 1 : 0;
-  {
+  if (b >= PEER_TILE_MIN) {
+    // large batches: the k best peers of every new node by the exact
+    // graph's brute-force tiles (matrix cores), then merged with its search
+    // result; the same distances and (distance, id) order as k_peers
+    knng_status s = exact_lists_range(g, n, b, n, b, true, pa.list_ids, pa.list_d, S.k_pad,
+                                      stream, true, KNNG_STAGE_PEERS);
+    if (s != KNNG_OK) return s;
+    Timed t(g, KNNG_STAGE_PEERS, stream);
+    KNNG_TRY(launch_merge_lists(pa.list_ids, pa.list_d, res_ids, res_d, S.k_pad, S.k, b, S.pad,
+                                stream),
+             "merge launch");
+  } else {
     Timed t(g, KNNG_STAGE_PEERS, stream);
     KNNG_TRY(launch_peers(pa, stream), "peers launch");
   }

@@ -224,14 +224,14 @@ def test_search_float32_scores_follow_oracle(G):
 
 
 @pytest.mark.parametrize("score,batches", [("bf16", [256, 100, 1]), ("bf16m", [256, 100, 1]),
-                                            ("exact", [256, 77]),
+                                            ("exact", [256, 77]), ("exact", [1100]),
                                            ("fp8", [128])])
 def test_insert_float(G, score, batches):
     import torch
     n0, dim, k = 2000, 96, 10
     total = n0 + sum(batches)
     X = f32_points(41, total, dim)
-    cfg = cfg_for(G, dim, k, total, 256, score=score, speedup=8)
+    cfg = cfg_for(G, dim, k, total, max(batches), score=score, speedup=8)
     say(f"float inserts score={score} batches={batches}")
     g = G.KnnGraph.build_exact(cfg, torch.from_numpy(X[:n0]).cuda())
     o_ids, o_d = O.exact_graph(X[:n0], k)

@@ -171,6 +171,15 @@ def test_batched_inserts_bit_exact(G, batches, depth):
     _run_inserts(G, X, 6000, batches, 10, 12, depth=depth)
 
 
+def test_large_batch_peers_on_tiles_bit_exact(G):
+    """Batches of 1,024 points or more score their peers with the exact
+    graph's tiles instead of one wavefront per point: same graph, bit for
+    bit."""
+    X = u8_points(14, 3000 + 1100, 16, clusters=6, sigma=12.0)
+    say("large batch: peers on the exact tiles")
+    _run_inserts(G, X, 3000, [1100], 10, 12, depth=2)
+
+
 def test_batched_inserts_then_queries_k20(G):
     X = u8_points(12, 3200, 32, clusters=4)
     g, og = _run_inserts(G, X, 3000, [128, 72], 20, 6)

@@ -513,6 +513,14 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
     // searches per launch) and costs a lone wavefront its extra
     // instructions.
     constexpr bool REUSE = KEEP && !PART;
+    // One gather-issue site after the step's branches when a step gathers
+    // its rows in one pass group (fewer registers: 244 instead of 252-366
+    // VGPRs for bfloat16 rows of 128 coordinates); steps of several
+    // double-buffered pass groups allocate better with the issue inlined in
+    // the move and window branches (with one site, 40-150 VGPRs spilled for
+    // bfloat16 rows of 512 and FP8 rows of 960 coordinates; none without).
+    constexpr bool ONE_ISSUE = NG == 1;
+    static_assert(ONE_ISSUE || !REUSE, "kept window scores need the single issue site");
     uint32_t sd = 0xffffffffu;      // kept scores, lane view of the next window
     int nsave = 0;                  // (uniform) positions kept at the last acceptance
     int skip = 0;                   // (uniform) leading positions of this window kept
@@ -764,26 +772,40 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
             }
           }
           ++list_reads;
+          if constexpr (!ONE_ISSUE) issue();
         } else if (!climbing) {
           const uint32_t x63 = (uint32_t)readlane_i32((int32_t)xL, WAVE - 1);
           P += WAVE;
           xP = (lcg.a * x63 + lcg.c) & mmask;
-          if (P >= a.m_mod) done = true;
-          else draw = true;
           nsave = 0;
+          if (P >= a.m_mod) {
+            done = true;
+          } else if constexpr (ONE_ISSUE) {
+            draw = true;
+          } else {
+            window();
+            issue();
+          }
         } else if (GNNS && restarts_used >= a.restarts) {
           done = true;             // local maximum after the last restart
         } else {
           climbing = false;        // local maximum: restart
-          draw = true;
+          if constexpr (ONE_ISSUE) {
+            draw = true;
+          } else {
+            window();
+            issue();
+          }
         }
-        // a window drawn after a climb resumes the kept positions
-        skip = draw ? nsave : 0;
-        if (draw) {
-          nsave = 0;
-          window();
+        if constexpr (ONE_ISSUE) {
+          // a window drawn after a climb resumes the kept positions
+          skip = draw ? nsave : 0;
+          if (draw) {
+            nsave = 0;
+            window();
+          }
+          if (!done) issue();
         }
-        if (!done) issue();
       }
 
       // bookkeeping of this step: visited, trace, result list, count

@@ -63,7 +63,16 @@ def _rows(directory: str, suffix: str):
 
 def _short(name: str) -> str:
     name = name.strip('"')
-    return name if len(name) < 90 else name[:87] + "..."
+    return name if len(name) < 150 else name[:147] + "..."
+
+
+def _base(name: str) -> str:
+    """The kernel function's name without its template arguments."""
+    name = name.strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    cut = [i for i in (name.find("<"), name.find("(")) if i >= 0]
+    return name[:min(cut)] if cut else name
 
 
 def kernel_table(directory: str):
@@ -101,6 +110,14 @@ def write_trace(directory: str, out: str, command: str) -> None:
               "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
     for name, v in sorted(by_kernel.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{_short(name)}` | {len(v)} | {sum(v) / len(v):.1f} | {sum(v):.1f} | "
+                     f"{100 * sum(v) / total:.1f} |")
+    by_base = defaultdict(list)
+    for name, v in by_kernel.items():
+        by_base[_base(name)].extend(v)
+    lines += ["", "Per kernel function, all instantiations and grids:", "",
+              "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
+    for name, v in sorted(by_base.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {len(v)} | {sum(v) / len(v):.1f} | {sum(v):.1f} | "
                      f"{100 * sum(v) / total:.1f} |")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -117,7 +117,7 @@ WORKLOADS: dict[str, Workload] = {
         name="serve-f32-d96-1m-2m", kind="f32", dim=96, k=10, n_initial=1_000_000,
         n_insert=1_000_000, batch=16384, n_query=0, n_clusters=2000,
         mixture_seed=41, stream_seed=42, query_seed=43, subspace_rank=3,
-        speedup=18, expansion_num=3, expansion_den=2, depth=3, score="bf16"),
+        speedup=22, expansion_num=5, expansion_den=4, depth=3, score="bf16"),
     # The same sizes with isotropic 96-dimensional components (sigma ~ U[0.05,
     # 0.3] in every coordinate): kept for the measurements that show why the
     # serving workload uses low-dimensional components.

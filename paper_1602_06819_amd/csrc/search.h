@@ -419,6 +419,18 @@ template <class Score, int G, int CPL, int LROW, bool GVIS, int CCPL, int CPB, i
 __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint64_t tk_c[WAVE], tk_r[K2 ? 2 * WAVE : WAVE], tk_o[K2 ? 2 * WAVE : WAVE];
+  // With the visited set in global memory, a filter in LDS of the nodes the
+  // climb has evaluated.  A restart candidate is drawn from a permutation,
+  // so it never repeats an earlier restart: it can only have been visited
+  // by a climb step, and when its filter bit is clear it was not; the
+  // global set is probed only for the others (and for every list-scan
+  // candidate).
+  constexpr bool FILT = GVIS && KEEP;
+  constexpr int FILT_WORDS = FILT ? 2048 : 1;     // 64 Kbit
+  __shared__ uint32_t filt[FILT_WORDS];
+  auto filt_bit = [](int32_t id) __attribute__((always_inline)) {
+    return ((uint32_t)id * 0x9E3779B1u) >> (32 - 16);
+  };
   static_assert(G % PB == 0, "pass groups must divide the passes");
   constexpr int NG = G / PB;                      // pass groups per step
   constexpr int NB = NG > 1 ? 2 : 1;              // register buffers
@@ -449,6 +461,9 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
     if (GVIS) {
       for (int w = lane * 4; w < a.vis_words_pad; w += WAVE * 4)
         *reinterpret_cast<v4i*>(vis + w) = v4i{0, 0, 0, 0};
+      if (FILT)
+        for (int w = lane * 4; w < FILT_WORDS; w += WAVE * 4)
+          *reinterpret_cast<v4i*>(filt + w) = v4i{0, 0, 0, 0};
       __threadfence();
     } else {
       for (int w = lane; w < a.vis_words; w += WAVE) vis[w] = 0u;
@@ -609,8 +624,16 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
       const int32_t cand = spaced ? cidG[0] : cidL;   // this lane's candidate
       const bool owner = !spaced || sub == 0;
       // visited probe of this lane's candidate while the gathers fly
-      const bool seen = GVIS ? gbit_test(vis, cand >= 0 ? cand : 0)
-                             : bit_test(vis, cand >= 0 ? cand : 0);
+      bool seen;
+      if constexpr (FILT) {
+        const int32_t cc = cand >= 0 ? cand : 0;
+        const uint32_t fb = filt_bit(cc);
+        const bool maybe = climbing || ((filt[fb >> 5] >> (fb & 31)) & 1u);
+        seen = maybe && gbit_test(vis, cc);
+      } else {
+        seen = GVIS ? gbit_test(vis, cand >= 0 ? cand : 0) : bit_test(vis, cand >= 0 ? cand : 0);
+      }
+      const bool climb_step = climbing;
       // distances of the group-view candidates; stage their adjacency rows.
       // A list scan has at most k candidates: when they fit in fewer passes
       // than G, only those passes are computed.
@@ -810,6 +833,10 @@ __global__ __launch_bounds__(64, WPE) void k_search(SearchArgs a) {
 
       // bookkeeping of this step: visited, trace, result list, count
       if (mine) atomicOr(&vis[cid_now >> 5], 1u << (cid_now & 31));
+      if (FILT && mine && climb_step) {
+        const uint32_t fb = filt_bit(cid_now);
+        atomicOr(&filt[fb >> 5], 1u << (fb & 31));
+      }
       if (R.trace && mine) {
         const int r = rank_below(C);
         if (evals + r < R.trace_stride) R.trace[trace_base + evals + r] = cid_now;

@@ -314,16 +314,20 @@ def test_long_rows_search_and_insert(G, score, dim, k):
     check_error(Xall, Xall, gi, gd)
 
 
-def test_large_launch_equals_small_launches(G):
+@pytest.mark.parametrize("n,dim,speedup,e", [(6000, 96, 6, (3, 2)), (400_000, 16, 100, (5, 4))])
+def test_large_launch_equals_small_launches(G, n, dim, speedup, e):
     """Launches of 2,048 searches or more keep the scored positions of a
     restart window across the climb it starts (rows of up to 96 coordinates,
-    lists of up to 16 ids); smaller launches rescore them.  Both must give
-    the same results, evaluation order included."""
+    lists of up to 16 ids), and on graphs whose visited sets live in global
+    memory (above ~327k nodes) skip the visited probe of restart candidates
+    that an LDS filter of the climbs' evaluations clears; smaller launches
+    do neither.  Both must give the same results, evaluation order
+    included."""
     import torch
-    n, dim, k, m = 6000, 96, 10, 2304
+    k, m = 10, 2304
     X = f32_points(81, n + m, dim)
     base, Q = X[:n], X[n:]
-    cfg = cfg_for(G, dim, k, n, m, speedup=6, e=(3, 2))
+    cfg = cfg_for(G, dim, k, n, m, speedup=speedup, e=e)
     say(f"large vs small search launches n={n} m={m}")
     g = G.KnnGraph.build_exact(cfg, torch.from_numpy(base).cuda())
     keys = torch.arange(77, 77 + m, dtype=torch.int64)

@@ -30,6 +30,13 @@
 // their lists with two bitonic merges over lane shuffles.  KM >= k entries
 // are a superset of the top k.
 //
+// Selection (uint8).  A candidate whose distance is above the lane's list
+// end cannot enter; the few that can are queued in LDS while a query
+// tile's 16-row blocks are scored, then inserted: every lane takes its
+// queued keys in order, so the wavefront runs as many insertions as the
+// longest queue rather than one for every position where some lane had a
+// candidate.  The kept set is the KM smallest keys either way.
+//
 // Splits (uint8).  When there are few queries, blockIdx.y splits the
 // database into ranges; each writes a partial list and k_split_merge
 // merges them.
@@ -40,6 +47,19 @@
 #include "internal.h"
 
 namespace knng {
+
+// Insert `cand` (< L[KM - 1]) into the ascending list L: every slot is
+// compared with the old list at once (the comparisons are monotone in the
+// slot), then each slot takes its own key, its left neighbour's or cand.
+template <int KM>
+__device__ __forceinline__ void reg_list_place(uint64_t (&L)[KM], uint64_t cand) {
+  bool c[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) c[j] = cand < L[j];
+#pragma unroll
+  for (int j = KM - 1; j >= 1; --j) L[j] = c[j - 1] ? L[j - 1] : (c[j] ? cand : L[j]);
+  L[0] = c[0] ? cand : L[0];
+}
 
 template <bool F32, int QT, int DT, int KM, int NCH>
 __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
@@ -55,6 +75,9 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
   if (d_end > a.nd) d_end = a.nd;
   const char* qrows = (const char*)a.qvec;
   const char* drows = (const char*)a.dvec;
+  // uint8: queued keys of one query tile, slot-major (slot * 256 + thread)
+  constexpr int NQ = F32 ? 1 : 4 * DT;
+  __shared__ uint64_t queue[NQ * 256];
 
   // query operands (B), kept in registers
   vec4 bq[QT][NCH];
@@ -111,6 +134,7 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
     }
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
+      int nq = 0;                   // uint8: keys queued for this query tile
 #pragma unroll
       for (int dt = 0; dt < DT; ++dt) {
         uint32_t dist[4];
@@ -141,17 +165,28 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          // (the screen pays on the int8 tiles; on the float32 tiles the
-          // branch costs more than it saves, measured)
-          if (F32 || dist[rr] <= thr[t]) {
-            int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+          const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+          if constexpr (F32) {
+            // (no screen: on the float32 tiles the branch costs more than it
+            // saves, measured)
             bool ok = orow < d_end &&
                       !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t]);
             uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
-            if (key < L[t][KM - 1]) {
-              reg_list_insert<KM>(L[t], key);
-              if constexpr (!F32) thr[t] = key_dist(L[t][KM - 1]);
-            }
+            if (key < L[t][KM - 1]) reg_list_insert<KM>(L[t], key);
+          } else if (dist[rr] <= thr[t] && orow < d_end &&
+                     !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t])) {
+            queue[nq * 256 + threadIdx.x] = make_key(dist[rr], a.d_id_base + orow);
+            ++nq;
+          }
+        }
+      }
+      if constexpr (!F32) {
+        // the queue in arrival order (nq <= 4 DT slots)
+        for (int r = 0; r < nq; ++r) {
+          const uint64_t key = queue[r * 256 + threadIdx.x];
+          if (key < L[t][KM - 1]) {
+            reg_list_place<KM>(L[t], key);
+            thr[t] = key_dist(L[t][KM - 1]);
           }
         }
       }

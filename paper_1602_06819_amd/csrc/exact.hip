@@ -100,13 +100,17 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
   }
 
   uint64_t L[QT][KM];
-  // distance bits of each list's last entry: candidates above it cannot
-  // enter, so most int8 candidates are rejected by one 32-bit compare before
-  // a key is built
-  uint32_t thr[QT];
+  // uint8 screen: a row can enter only if its distance |q|^2 + (|x|^2 - 2 q.x)
+  // is at most the list end's, so the per-row part |x|^2 - 2 q.x is compared
+  // with thq = min(list end, SCREEN_CAP) - |q|^2 before anything else is
+  // computed.  Every uint8 distance is below 256 * 255^2 < SCREEN_CAP; rows
+  // outside the tile range take the norm FAR_NORM, whose per-row part
+  // (|2 q.x| <= 2 * 256 * 128^2) stays above any thq.
+  constexpr int32_t SCREEN_CAP = 1 << 29, FAR_NORM = 1 << 30;
+  int32_t thq[QT];
 #pragma unroll
   for (int t = 0; t < QT; ++t) {
-    thr[t] = 0xffffffffu;
+    thq[t] = SCREEN_CAP - (int32_t)qn[t];
 #pragma unroll
     for (int j = 0; j < KM; ++j) L[t][j] = KEY_INF;
   }
@@ -132,13 +136,22 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
         dn[dt][rr] = a.dnorm[orow < a.nd ? orow : a.nd - 1];
       }
     }
+    if constexpr (!F32) {
+      if (d0 + 16 * DT > d_end) {   // the range's last tile (wave-uniform)
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            if (d0 + 16 * dt + 4 * grp + rr >= d_end) dn[dt][rr] = (uint32_t)FAR_NORM;
+      }
+    }
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       int nq = 0;                   // uint8: keys queued for this query tile
 #pragma unroll
       for (int dt = 0; dt < DT; ++dt) {
-        uint32_t dist[4];
         if constexpr (F32) {
+          uint32_t dist[4];
           v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < NCH; ++c)
@@ -154,29 +167,32 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
               dist[rr] = __float_as_uint(v > 0.f ? v : 0.f);
             }
           }
+          // (no screen: on the float32 tiles the branch costs more than it
+          // saves, measured)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+            bool ok = orow < d_end &&
+                      !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t]);
+            uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
+            if (key < L[t][KM - 1]) reg_list_insert<KM>(L[t], key);
+          }
         } else {
           v4i acc = v4i{0, 0, 0, 0};
 #pragma unroll
           for (int c = 0; c < NCH; ++c)
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[dt][c], bq[t][c], acc, 0, 0, 0);
 #pragma unroll
-          for (int rr = 0; rr < 4; ++rr)
-            dist[rr] = (uint32_t)((int32_t)qn[t] + (int32_t)dn[dt][rr] - 2 * acc[rr]);
-        }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
-          if constexpr (F32) {
-            // (no screen: on the float32 tiles the branch costs more than it
-            // saves, measured)
-            bool ok = orow < d_end &&
-                      !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t]);
-            uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
-            if (key < L[t][KM - 1]) reg_list_insert<KM>(L[t], key);
-          } else if (dist[rr] <= thr[t] && orow < d_end &&
-                     !(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t])) {
-            queue[nq * 256 + threadIdx.x] = make_key(dist[rr], a.d_id_base + orow);
-            ++nq;
+          for (int rr = 0; rr < 4; ++rr) {
+            const int32_t part = (int32_t)dn[dt][rr] - 2 * acc[rr];
+            if (part <= thq[t]) {
+              const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
+              if (!(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t])) {
+                queue[nq * 256 + threadIdx.x] =
+                    make_key((uint32_t)((int32_t)qn[t] + part), a.d_id_base + orow);
+                ++nq;
+              }
+            }
           }
         }
       }
@@ -186,7 +202,8 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
           const uint64_t key = queue[r * 256 + threadIdx.x];
           if (key < L[t][KM - 1]) {
             reg_list_place<KM>(L[t], key);
-            thr[t] = key_dist(L[t][KM - 1]);
+            const uint32_t e = key_dist(L[t][KM - 1]);
+            thq[t] = (e < (uint32_t)SCREEN_CAP ? (int32_t)e : SCREEN_CAP) - (int32_t)qn[t];
           }
         }
       }

@@ -328,6 +328,10 @@ def bench_batches(args, w) -> dict:
     # ---- the naive method (Section 2.1) on the same GPU: the same batches -----------
     naive = None
     if not args.no_naive:
+        gw = KnnGraph.build_exact(cfg, Xd[:n0])      # untimed warmup batch
+        gw.insert_exact(Xd[n0:n0 + b])
+        gw.close()
+        del gw
         gn = KnnGraph.build_exact(cfg, Xd[:n0])
         torch.cuda.synchronize()
         tn0 = time.perf_counter()

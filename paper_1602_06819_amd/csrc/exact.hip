@@ -62,7 +62,7 @@ __device__ __forceinline__ void reg_list_place(uint64_t (&L)[KM], uint64_t cand)
 }
 
 template <bool F32, int QT, int DT, int KM, int NCH>
-__global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
+__global__ __launch_bounds__(256, (!F32 && KM == 16 && NCH == 1) ? 3 : 1) void k_exact(ExactArgs a) {
   typedef typename std::conditional<F32, v4f, v4i>::type vec4;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -148,9 +148,9 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
 #pragma unroll
     for (int t = 0; t < QT; ++t) {
       int nq = 0;                   // uint8: keys queued for this query tile
+      if constexpr (F32) {
 #pragma unroll
-      for (int dt = 0; dt < DT; ++dt) {
-        if constexpr (F32) {
+        for (int dt = 0; dt < DT; ++dt) {
           uint32_t dist[4];
           v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -177,14 +177,22 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs a) {
             uint64_t key = ok ? make_key(dist[rr], a.d_id_base + orow) : KEY_INF;
             if (key < L[t][KM - 1]) reg_list_insert<KM>(L[t], key);
           }
-        } else {
-          v4i acc = v4i{0, 0, 0, 0};
+        }
+      } else {
+        // every block's MFMAs first, so no result is read right after issue
+        v4i acc[DT];
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt) {
+          acc[dt] = v4i{0, 0, 0, 0};
 #pragma unroll
           for (int c = 0; c < NCH; ++c)
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[dt][c], bq[t][c], acc, 0, 0, 0);
+            acc[dt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[dt][c], bq[t][c], acc[dt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int dt = 0; dt < DT; ++dt) {
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) {
-            const int32_t part = (int32_t)dn[dt][rr] - 2 * acc[rr];
+            const int32_t part = (int32_t)dn[dt][rr] - 2 * acc[dt][rr];
             if (part <= thq[t]) {
               const int32_t orow = d0 + 16 * dt + 4 * grp + rr;
               if (!(a.exclude_self && a.d_id_base + orow == a.q_id_base + qid[t])) {
